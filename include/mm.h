@@ -1,0 +1,309 @@
+/*
+ * mm.h -- C ABI of libmm, dense matrix multiplication C = A.B on MI355X (gfx950).
+ *
+ * The operation is the textbook product of the paper's section III: for an
+ * M x K matrix A and a K x N matrix B (the paper's m x n and n x p), every
+ * entry of the M x N result is the dot product of a row of A with a column of
+ * B, C[i][j] = sum_k A[i][k] * B[k][j].  Storage is row-major, as in C (the
+ * storage remark of section III): element (r, c) of a matrix with leading
+ * dimension ld sits at base[r * ld + c].  There is no alpha/beta: C is
+ * overwritten with A.B.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Pointers named A, B, C, X, workspace are DEVICE pointers (memory of the
+ *    current HIP device, e.g. from hipMalloc or a torch CUDA tensor).  Pointers
+ *    to descriptors, configs and outputs such as id_out are HOST pointers
+ *    unless stated otherwise.
+ *  * Ownership: the caller owns every buffer it passes and must keep it alive
+ *    until the enqueued work has finished.  The library never frees caller
+ *    memory.  Objects the library creates (plans, servers) are released only by
+ *    their *_destroy call.
+ *  * Streams: `stream` is a hipStream_t passed as void*; NULL means the legacy
+ *    default stream.  GEMM calls only enqueue work and return at once; device
+ *    faults surface at the next synchronising call.
+ *  * Errors: argument checks are synchronous and return a negative mm_status
+ *    without enqueueing anything; mm_last_error() then describes the failure
+ *    (thread-local).  No C++ exception crosses this interface.
+ *  * Degenerate sizes: M == 0 or N == 0 is a no-op returning MM_OK; K == 0
+ *    writes C := 0 (an empty sum).
+ *  * Leading dimensions must satisfy lda >= max(K,1), ldb >= max(N,1),
+ *    ldc >= max(N,1); C must not overlap A or B.
+ *  * Calls on distinct streams may run concurrently from any threads.
+ */
+#ifndef MM_H
+#define MM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum mm_status {
+    MM_OK = 0,
+    MM_E_INVAL = -1,        /* bad argument: sizes, leading dimensions, null or overlapping pointers */
+    MM_E_NOMEM = -2,        /* device allocation failed, or a request larger than a server budget */
+    MM_E_DEVICE = -3,       /* a HIP runtime call failed */
+    MM_E_BUSY = -4,         /* server queue full */
+    MM_E_UNSUPPORTED = -5,  /* valid but not implemented combination (e.g. wrong GPU architecture) */
+    MM_E_TIMEOUT = -6       /* mm_serve_wait ran out of time; the request is still pending */
+} mm_status;
+
+/* How a product is computed. */
+typedef enum mm_method {
+    MM_F64 = 0,           /* binary64 operands, binary64 MFMA, binary64 accumulation */
+    MM_F32 = 1,           /* FP32 operands, FP32 MFMA, FP32 accumulation */
+    MM_SPLIT_BF16_3 = 2,  /* FP32 operands as 2 bfloat16 planes, 3 plane products */
+    MM_SPLIT_BF16_6 = 3   /* FP32 operands as 3 bfloat16 planes, 6 plane products */
+} mm_method;
+
+/* Library version and the GPU architecture the kernels were built for. */
+const char *mm_version(void);
+
+/* Text for a status code; never NULL. */
+const char *mm_status_string(mm_status s);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *mm_last_error(void);
+
+/* Check that the current device is a gfx950 and warm the library's per-device
+ * state.  Returns MM_E_UNSUPPORTED on another architecture.  Optional: every
+ * entry point initialises lazily. */
+mm_status mm_init(int device);
+
+/*
+ * mm_gemm_f64 -- C = A.B in binary64 (section III's sum, every product and
+ * partial sum in binary64 on the FP64 matrix cores).
+ *   M, N, K   : A is M x K, B is K x N, C is M x N (row-major, leading dims lda, ldb, ldc)
+ *   A, B      : device, read-only;  C : device, overwritten
+ *   stream    : hipStream_t or NULL
+ * Summation order differs from a serial loop; the result of each entry lies
+ * within 4*K*2^-53*(|A||B|)_ij of the exact sum and is exact whenever every
+ * partial sum is representable (e.g. small integers).  For a fixed shape the
+ * result is deterministic (no atomics, no split-K).
+ */
+mm_status mm_gemm_f64(int64_t M, int64_t N, int64_t K,
+                      const double *A, int64_t lda,
+                      const double *B, int64_t ldb,
+                      double *C, int64_t ldc, void *stream);
+
+/* mm_gemm_f32 -- as mm_gemm_f64 with FP32 operands, FP32 MFMA and FP32
+ * accumulation; per-entry error within 4*K*2^-24*(|A||B|)_ij. */
+mm_status mm_gemm_f32(int64_t M, int64_t N, int64_t K,
+                      const float *A, int64_t lda,
+                      const float *B, int64_t ldb,
+                      float *C, int64_t ldc, void *stream);
+
+/*
+ * mm_split_bf16 -- the split step on its own: writes the FP32 matrix X
+ * (rows x cols, leading dim ldx) as `nplanes` bfloat16 planes, plane 0 =
+ * bf16_rne(x), plane p = bf16_rne(x - plane_0 - ... - plane_{p-1}) with the
+ * leftovers formed exactly in FP32.  Plane p of element (r, c) is stored at
+ *   planes[p * plane_stride + r * cols + c]            (transpose == 0)
+ *   planes[p * plane_stride + c * rows + r]            (transpose != 0)
+ * as raw bfloat16 bits.  planes: device, caller-owned, at least
+ * nplanes * plane_stride elements; plane_stride >= rows * cols.
+ * nplanes in {1, 2, 3}.  Non-finite inputs and |x| at or above the largest
+ * bfloat16 are outside the contract.
+ */
+mm_status mm_split_bf16(int64_t rows, int64_t cols, const float *X, int64_t ldx,
+                        int32_t nplanes, int32_t transpose,
+                        uint16_t *planes, int64_t plane_stride, void *stream);
+
+/* Bytes of device workspace mm_gemm_split_bf16 needs for this shape. */
+size_t mm_split_workspace_bytes(int64_t M, int64_t N, int64_t K, int32_t nprod);
+
+/*
+ * mm_gemm_split_bf16 -- C = A.B for FP32 operands on the bfloat16 matrix
+ * cores.  A and B are split into bfloat16 planes (2 planes for nprod = 3,
+ * 3 planes for nprod = 6, as mm_split_bf16), the plane products
+ *   nprod = 3: hi.hi + hi.lo + lo.hi
+ *   nprod = 6: h.h + h.m + m.h + h.l + m.m + l.h
+ * are accumulated in FP32 in two accumulator sets (the leading h.h product and
+ * the sum of the corrections), and each entry is recombined in binary64 as
+ * (double)lead + (double)corr before being stored.
+ *   C         : device; FP32 (c_is_f64 == 0) or binary64 (c_is_f64 != 0), ldc in elements
+ *   workspace : device scratch of at least mm_split_workspace_bytes(M,N,K,nprod)
+ *               bytes, or NULL to let the library allocate it stream-ordered
+ * Design error against the exact product: about 4e-6 normwise for nprod = 3 on
+ * zero-mean data, below 1e-6 for nprod = 6.  nprod not in {3, 6} is MM_E_INVAL.
+ */
+mm_status mm_gemm_split_bf16(int64_t M, int64_t N, int64_t K,
+                             const float *A, int64_t lda,
+                             const float *B, int64_t ldb,
+                             void *C, int64_t ldc, int32_t c_is_f64,
+                             int32_t nprod, void *workspace, size_t workspace_bytes,
+                             void *stream);
+
+/*
+ * mm_residual_f64 -- the residual probe of a computed product (Freivalds):
+ * for a caller-chosen probe vector x (binary64, length N, device) computes
+ * y = B.x, z = A.y, w = C.x and r = w - z, all in binary64, and stores
+ *   out[0] = ||r||_2^2,  out[1] = ||z||_2^2          (out: device, 2 doubles)
+ * so sqrt(out[0]/out[1]) is the relative residual of C.  in_dtype selects the
+ * element type of A and B and c_dtype that of C: 0 = binary64, 1 = FP32.
+ * workspace: device, at least mm_residual_workspace_bytes(M, N, K) bytes, or
+ * NULL for stream-ordered allocation by the library.  The reduction order is
+ * fixed, so the result is deterministic.
+ */
+size_t mm_residual_workspace_bytes(int64_t M, int64_t N, int64_t K);
+mm_status mm_residual_f64(int64_t M, int64_t N, int64_t K,
+                          const void *A, int64_t lda, const void *B, int64_t ldb,
+                          const void *C, int64_t ldc, int32_t in_dtype, int32_t c_dtype,
+                          const double *x, double *out,
+                          void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
+/* Grouped products: many independent C_i = A_i.B_i of different shapes in   */
+/* one persistent kernel launch.                                             */
+/* ------------------------------------------------------------------------ */
+
+/* One problem: device operands, row-major, same rules as mm_gemm_*.  The element
+ * type follows the method: binary64 for MM_F64, FP32 otherwise (C is FP32 for
+ * every FP32-input method). */
+typedef struct mm_problem {
+    int64_t M, N, K;
+    const void *A; int64_t lda;
+    const void *B; int64_t ldb;
+    void *C;       int64_t ldc;
+} mm_problem;
+
+typedef struct mm_grouped_plan mm_grouped_plan;
+
+/*
+ * mm_gemm_grouped -- C_i = A_i.B_i for i < count (host array `probs`), all
+ * with the same method, each result identical to what the single-problem
+ * entry point with the same tile configuration returns.
+ *   plan_inout: NULL runs once (descriptors are uploaded and freed after the
+ *     launch, stream-ordered).  Otherwise *plan_inout is a plan cache: if it is
+ *     NULL a plan is built for these shapes (tile map, device descriptor
+ *     buffers, split workspace, and a HIP graph of the whole sequence captured
+ *     on `stream`) and returned; if it is an existing plan whose shapes match,
+ *     only the operand pointers are refreshed and the graph is replayed.  A
+ *     plan whose shapes differ is MM_E_INVAL.  A plan is owned by the caller
+ *     and freed with mm_grouped_plan_destroy after its last launch finished.
+ * count == 0 is a no-op.  Problems with M == 0 or N == 0 are skipped.
+ */
+mm_status mm_gemm_grouped(const mm_problem *probs, int32_t count, mm_method method,
+                          mm_grouped_plan **plan_inout, void *stream);
+mm_status mm_grouped_plan_destroy(mm_grouped_plan *plan);
+
+/* Tile configuration the plan chose (autotuned or default) and its tile count. */
+mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out,
+                               int64_t *tiles_out, int32_t *uses_graph_out);
+
+/* ------------------------------------------------------------------------ */
+/* Tile configurations and the autotuner.                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Number of compiled tile variants for a method, and the tile sizes of one. */
+int32_t mm_variant_count(mm_method method);
+mm_status mm_variant_info(mm_method method, int32_t variant, int32_t *bm, int32_t *bn, int32_t *bk);
+
+/* The variant the library will use for (method, M, N, K): the autotune cache
+ * entry of the shape bucket if present, else a fixed default.  A pure
+ * function of its arguments and the loaded cache. */
+int32_t mm_select_variant(mm_method method, int64_t M, int64_t N, int64_t K);
+
+/* Run a single product with an explicit variant (for tuning and tests).
+ * Operand element types follow `method`; workspace as mm_gemm_split_bf16. */
+mm_status mm_gemm_variant(mm_method method, int32_t variant,
+                          int64_t M, int64_t N, int64_t K,
+                          const void *A, int64_t lda, const void *B, int64_t ldb,
+                          void *C, int64_t ldc, void *workspace, size_t workspace_bytes,
+                          void *stream);
+
+/*
+ * mm_autotune -- time every variant of `method` on the caller's operands
+ * (device, M x K / K x N / M x N as for mm_gemm_variant; C is overwritten) with
+ * `warmup` untimed and `reps` timed launches each (HIP events, median), store
+ * the fastest in the cache under the shape's bucket and return it in
+ * *variant_out (and its median time in ms in *ms_out, nullable).  The bucket is
+ * (method, ceil(log2 M), ceil(log2 N), ceil(log2 K)).  Runs synchronously on
+ * `stream`.
+ */
+mm_status mm_autotune(mm_method method, int64_t M, int64_t N, int64_t K,
+                      const void *A, int64_t lda, const void *B, int64_t ldb,
+                      void *C, int64_t ldc, int32_t warmup, int32_t reps,
+                      int32_t *variant_out, double *ms_out, void *stream);
+
+/* Persist / restore the autotune cache as JSON (keyed by architecture).  Loading
+ * a file written for another architecture or library version is MM_E_INVAL
+ * and leaves the cache unchanged. */
+mm_status mm_autotune_save(const char *path);
+mm_status mm_autotune_load(const char *path);
+mm_status mm_autotune_clear(void);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: a continuous-batching request loop.                              */
+/* ------------------------------------------------------------------------ */
+
+typedef struct mm_server mm_server;
+
+typedef struct mm_serve_config {
+    uint64_t budget_bytes;   /* admission budget: bytes of operands, results and workspace in flight */
+    int32_t slots;           /* concurrent launch slots (one HIP stream each), 1..8 */
+    int32_t max_batch;       /* most requests packed into one grouped launch */
+    int32_t queue_capacity;  /* most requests waiting for admission; submit beyond it is MM_E_BUSY */
+    int32_t device;          /* HIP device ordinal */
+} mm_serve_config;
+
+typedef struct mm_serve_stats_t {
+    uint64_t completed;       /* requests finished (ok or failed) */
+    uint64_t failed;          /* requests finished with an error */
+    double p50_ms, p99_ms;    /* nearest-rank latency percentiles, arrival -> completion */
+    double mean_ms, max_ms;
+    double useful_flop;       /* sum of 2*M*N*K over completed requests */
+    double first_arrival_s;   /* server clock */
+    double last_done_s;
+    double tflops;            /* useful_flop / (last_done - first_arrival) / 1e12 */
+    uint64_t peak_bytes;      /* largest admitted bytes in flight */
+    uint64_t launches;        /* grouped launches issued */
+    double mean_batch;        /* requests per launch */
+} mm_serve_stats_t;
+
+/*
+ * mm_serve_create -- start a server: a scheduler thread that admits queued
+ * requests in arrival order while bytes in flight plus the request's bytes fit
+ * in budget_bytes and a slot is free, packs the admitted requests into grouped
+ * launches (one per method present) on the free slot's stream, and retires
+ * them when the slot's completion event fires.  Requests that arrive while
+ * others run are admitted as soon as a slot and budget free up, so their work
+ * overlaps on the device.  The server allocates its split workspace inside the
+ * budget.
+ */
+mm_status mm_serve_create(const mm_serve_config *cfg, mm_server **out);
+
+/*
+ * mm_serve_submit -- enqueue C = A.B (device operands, caller-owned, valid
+ * until mm_serve_wait returns for this id).  method: MM_F64, MM_F32,
+ * MM_SPLIT_BF16_3 or MM_SPLIT_BF16_6.  arrival_s is the request's arrival
+ * time on the server clock (mm_serve_clock); latency is measured from it, so a
+ * client replaying a schedule charges queueing before submission too; pass a
+ * negative value for "now".  Thread-safe.  A request whose bytes exceed the
+ * whole budget is MM_E_NOMEM at submit; a full queue is MM_E_BUSY.
+ */
+mm_status mm_serve_submit(mm_server *srv, const mm_problem *req, mm_method method,
+                          double arrival_s, uint64_t *id_out);
+
+/* Wait up to timeout_us (negative: forever) for request id.  On MM_OK the
+ * request has finished: *req_status (nullable) is its own status and
+ * *latency_ms (nullable) its latency.  MM_E_TIMEOUT if still pending. */
+mm_status mm_serve_wait(mm_server *srv, uint64_t id, int64_t timeout_us,
+                        mm_status *req_status, double *latency_ms);
+
+/* Seconds since the server was created (monotonic clock). */
+double mm_serve_clock(const mm_server *srv);
+
+mm_status mm_serve_stats(mm_server *srv, mm_serve_stats_t *out);
+
+/* Stop accepting requests, finish those in flight, free everything. */
+mm_status mm_serve_destroy(mm_server *srv);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MM_H */

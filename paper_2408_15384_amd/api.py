@@ -1,0 +1,372 @@
+"""Python binding of libmm's C ABI (include/mm.h).
+
+Argument marshalling only: torch tensors become raw device pointers, leading
+dimensions and a hipStream_t; every step of every product runs in the HIP
+kernels of libmm.so.  There is no CPU fallback: without the built library or a
+GPU every call raises.
+
+torch is imported before libmm.so is loaded so that the library binds to the
+HIP runtime torch already mapped (both carry the soname libamdhip64.so.7), so
+torch's pointers and streams are valid inside the library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmm.so")
+
+MM_OK, MM_E_INVAL, MM_E_NOMEM, MM_E_DEVICE, MM_E_BUSY, MM_E_UNSUPPORTED, MM_E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6
+MM_F64, MM_F32, MM_SPLIT_BF16_3, MM_SPLIT_BF16_6 = 0, 1, 2, 3
+METHODS = {"f64": MM_F64, "f32": MM_F32, "split3": MM_SPLIT_BF16_3, "split6": MM_SPLIT_BF16_6}
+
+_lib = None
+
+
+class MMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{status}: {message}")
+        self.status = status
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("B", ctypes.c_void_p), ("ldb", ctypes.c_int64),
+                ("C", ctypes.c_void_p), ("ldc", ctypes.c_int64)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("budget_bytes", ctypes.c_uint64), ("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
+                ("queue_capacity", ctypes.c_int32), ("device", ctypes.c_int32)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [("completed", ctypes.c_uint64), ("failed", ctypes.c_uint64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double),
+                ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("useful_flop", ctypes.c_double), ("first_arrival_s", ctypes.c_double),
+                ("last_done_s", ctypes.c_double), ("tflops", ctypes.c_double),
+                ("peak_bytes", ctypes.c_uint64), ("launches", ctypes.c_uint64),
+                ("mean_batch", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+# (name, restype, argtypes) of every export declared in include/mm.h
+_i64, _i32, _p, _d, _sz, _u64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_double, ctypes.c_size_t, ctypes.c_uint64
+_st = ctypes.c_int
+EXPORTS = [
+    ("mm_version", ctypes.c_char_p, []),
+    ("mm_status_string", ctypes.c_char_p, [_st]),
+    ("mm_last_error", ctypes.c_char_p, []),
+    ("mm_init", _st, [ctypes.c_int]),
+    ("mm_gemm_f64", _st, [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
+    ("mm_gemm_f32", _st, [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p]),
+    ("mm_split_bf16", _st, [_i64, _i64, _p, _i64, _i32, _i32, _p, _i64, _p]),
+    ("mm_split_workspace_bytes", _sz, [_i64, _i64, _i64, _i32]),
+    ("mm_gemm_split_bf16", _st, [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i32, _i32, _p, _sz, _p]),
+    ("mm_residual_workspace_bytes", _sz, [_i64, _i64, _i64]),
+    ("mm_residual_f64", _st, [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i32, _i32, _p, _p, _p, _sz, _p]),
+    ("mm_gemm_grouped", _st, [ctypes.POINTER(Problem), _i32, _st, ctypes.POINTER(_p), _p]),
+    ("mm_grouped_plan_destroy", _st, [_p]),
+    ("mm_grouped_plan_info", _st, [_p, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
+    ("mm_variant_count", _i32, [_st]),
+    ("mm_variant_info", _st, [_st, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    ("mm_select_variant", _i32, [_st, _i64, _i64, _i64]),
+    ("mm_gemm_variant", _st, [_st, _i32, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _sz, _p]),
+    ("mm_autotune", _st, [_st, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i32, _i32,
+                          ctypes.POINTER(_i32), ctypes.POINTER(_d), _p]),
+    ("mm_autotune_save", _st, [ctypes.c_char_p]),
+    ("mm_autotune_load", _st, [ctypes.c_char_p]),
+    ("mm_autotune_clear", _st, []),
+    ("mm_serve_create", _st, [ctypes.POINTER(ServeConfig), ctypes.POINTER(_p)]),
+    ("mm_serve_submit", _st, [_p, ctypes.POINTER(Problem), _st, _d, ctypes.POINTER(_u64)]),
+    ("mm_serve_wait", _st, [_p, _u64, _i64, ctypes.POINTER(_st), ctypes.POINTER(_d)]),
+    ("mm_serve_clock", _d, [_p]),
+    ("mm_serve_stats", _st, [_p, ctypes.POINTER(ServeStats)]),
+    ("mm_serve_destroy", _st, [_p]),
+]
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libmm.so (after torch) and declare every export."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  -- binds libmm to torch's HIP runtime
+
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run __graft_entry__.build() or python -m paper_2408_15384_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, res, args in EXPORTS:
+        if not hasattr(lib, name):  # TEMPORARY while grouped/serving are being written
+            continue
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def lib() -> ctypes.CDLL:
+    return load_library()
+
+
+def check(status: int) -> None:
+    if status != MM_OK:
+        raise MMError(status, lib().mm_last_error().decode())
+
+
+def _stream(stream) -> int:
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ld(t, name) -> int:
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError(f"{name} must be row-major (unit column stride)")
+    return max(int(t.stride(0)), int(t.shape[1]), 1)
+
+
+def _shapes(A, B):
+    M, K = A.shape
+    K2, N = B.shape
+    if K != K2:
+        raise ValueError(f"inner dimensions differ: {tuple(A.shape)} x {tuple(B.shape)}")
+    return int(M), int(N), int(K)
+
+
+def gemm_f64(A, B, C=None, stream=None):
+    """C = A.B in binary64 on the FP64 matrix cores (mm_gemm_f64)."""
+    import torch
+    M, N, K = _shapes(A, B)
+    if A.dtype != torch.float64 or B.dtype != torch.float64:
+        raise TypeError("gemm_f64 needs float64 operands")
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    check(lib().mm_gemm_f64(M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
+                            C.data_ptr(), _ld(C, "C"), _stream(stream)))
+    return C
+
+
+def gemm_f32(A, B, C=None, stream=None):
+    """C = A.B in FP32 on the FP32 matrix cores (mm_gemm_f32)."""
+    import torch
+    M, N, K = _shapes(A, B)
+    if A.dtype != torch.float32 or B.dtype != torch.float32:
+        raise TypeError("gemm_f32 needs float32 operands")
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    check(lib().mm_gemm_f32(M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
+                            C.data_ptr(), _ld(C, "C"), _stream(stream)))
+    return C
+
+
+def split_bf16(X, nplanes: int, transpose: bool = False, out=None, stream=None):
+    """bfloat16 planes of FP32 X (mm_split_bf16), returned as int16 bit patterns
+    of shape (nplanes, rows, cols) or (nplanes, cols, rows) if transposed."""
+    import torch
+    rows, cols = X.shape
+    shape = (nplanes, cols, rows) if transpose else (nplanes, rows, cols)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.int16, device=X.device)
+    check(lib().mm_split_bf16(rows, cols, X.data_ptr(), _ld(X, "X"), nplanes, int(bool(transpose)),
+                              out.data_ptr(), rows * cols, _stream(stream)))
+    return out
+
+
+def split_workspace_bytes(M: int, N: int, K: int, nprod: int) -> int:
+    return int(lib().mm_split_workspace_bytes(M, N, K, nprod))
+
+
+def gemm_split_bf16(A, B, nprod: int = 6, C=None, out_dtype=None, workspace=None, stream=None):
+    """C = A.B for FP32 operands by the split method (mm_gemm_split_bf16)."""
+    import torch
+    M, N, K = _shapes(A, B)
+    if A.dtype != torch.float32 or B.dtype != torch.float32:
+        raise TypeError("gemm_split_bf16 needs float32 operands")
+    if C is None:
+        C = torch.empty((M, N), dtype=out_dtype or torch.float32, device=A.device)
+    if C.dtype not in (torch.float32, torch.float64):
+        raise TypeError("C must be float32 or float64")
+    ws_ptr, ws_bytes = 0, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    check(lib().mm_gemm_split_bf16(M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
+                                   C.data_ptr(), _ld(C, "C"), int(C.dtype == torch.float64), nprod,
+                                   ws_ptr or None, ws_bytes, _stream(stream)))
+    return C
+
+
+def residual_f64(A, B, C, x, out=None, workspace=None, stream=None):
+    """Device tensor [||C.x - A.(B.x)||^2, ||A.(B.x)||^2] in binary64 (mm_residual_f64)."""
+    import torch
+    M, N, K = _shapes(A, B)
+    if tuple(C.shape) != (M, N):
+        raise ValueError("C shape")
+    code = {torch.float64: 0, torch.float32: 1}
+    if A.dtype != B.dtype or A.dtype not in code or C.dtype not in code:
+        raise TypeError("A, B must share float64/float32; C float64/float32")
+    if x.dtype != torch.float64 or x.numel() != N:
+        raise ValueError("x must be float64 of length N")
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=A.device)
+    ws_ptr, ws_bytes = 0, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    check(lib().mm_residual_f64(M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"), C.data_ptr(),
+                                _ld(C, "C"), code[A.dtype], code[C.dtype], x.data_ptr(), out.data_ptr(),
+                                ws_ptr or None, ws_bytes, _stream(stream)))
+    return out
+
+
+def variant_count(method) -> int:
+    return int(lib().mm_variant_count(METHODS.get(method, method)))
+
+
+def variant_info(method, variant: int):
+    bm, bn, bk = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib().mm_variant_info(METHODS.get(method, method), variant, ctypes.byref(bm), ctypes.byref(bn),
+                                ctypes.byref(bk)))
+    return bm.value, bn.value, bk.value
+
+
+def select_variant(method, M, N, K) -> int:
+    return int(lib().mm_select_variant(METHODS.get(method, method), M, N, K))
+
+
+def gemm_variant(method, variant: int, A, B, C, workspace=None, stream=None):
+    M, N, K = _shapes(A, B)
+    ws_ptr, ws_bytes = 0, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    check(lib().mm_gemm_variant(METHODS.get(method, method), variant, M, N, K, A.data_ptr(), _ld(A, "A"),
+                                B.data_ptr(), _ld(B, "B"), C.data_ptr(), _ld(C, "C"), ws_ptr or None, ws_bytes,
+                                _stream(stream)))
+    return C
+
+
+def autotune(method, A, B, C, warmup: int = 2, reps: int = 5, stream=None):
+    """Time every variant on these operands; returns (variant, median ms)."""
+    M, N, K = _shapes(A, B)
+    v, ms = ctypes.c_int32(), ctypes.c_double()
+    check(lib().mm_autotune(METHODS.get(method, method), M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(),
+                            _ld(B, "B"), C.data_ptr(), _ld(C, "C"), warmup, reps, ctypes.byref(v),
+                            ctypes.byref(ms), _stream(stream)))
+    return v.value, ms.value
+
+
+def autotune_save(path: str) -> None:
+    check(lib().mm_autotune_save(path.encode()))
+
+
+def autotune_load(path: str) -> None:
+    check(lib().mm_autotune_load(path.encode()))
+
+
+def autotune_clear() -> None:
+    check(lib().mm_autotune_clear())
+
+
+def _problems(As: Sequence, Bs: Sequence, Cs: Sequence):
+    n = len(As)
+    arr = (Problem * max(n, 1))()
+    for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+        M, N, K = _shapes(A, B)
+        arr[i] = Problem(M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"), C.data_ptr(), _ld(C, "C"))
+    return arr, n
+
+
+class GroupedPlan:
+    """Owns an mm_grouped_plan (tile map, descriptors, captured graph)."""
+
+    def __init__(self, method):
+        self.method = METHODS.get(method, method)
+        self.handle = ctypes.c_void_p(None)
+
+    def run(self, As, Bs, Cs, stream=None):
+        arr, n = _problems(As, Bs, Cs)
+        check(lib().mm_gemm_grouped(arr, n, self.method, ctypes.byref(self.handle), _stream(stream)))
+        return Cs
+
+    def info(self):
+        v, t, g = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        check(lib().mm_grouped_plan_info(self.handle, ctypes.byref(v), ctypes.byref(t), ctypes.byref(g)))
+        return {"variant": v.value, "tiles": t.value, "graph": bool(g.value)}
+
+    def close(self):
+        if self.handle:
+            check(lib().mm_grouped_plan_destroy(self.handle))
+            self.handle = ctypes.c_void_p(None)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gemm_grouped(method, As, Bs, Cs, stream=None):
+    """One grouped launch without a plan (mm_gemm_grouped with plan_inout = NULL)."""
+    arr, n = _problems(As, Bs, Cs)
+    check(lib().mm_gemm_grouped(arr, n, METHODS.get(method, method), None, _stream(stream)))
+    return Cs
+
+
+class Server:
+    """A continuous-batching request loop (mm_serve_*)."""
+
+    def __init__(self, budget_bytes: int, slots: int = 4, max_batch: int = 64, queue_capacity: int = 1 << 16,
+                 device: int = 0):
+        cfg = ServeConfig(budget_bytes, slots, max_batch, queue_capacity, device)
+        self.handle = ctypes.c_void_p(None)
+        check(lib().mm_serve_create(ctypes.byref(cfg), ctypes.byref(self.handle)))
+
+    def clock(self) -> float:
+        return float(lib().mm_serve_clock(self.handle))
+
+    def submit(self, A, B, C, method, arrival_s: float = -1.0) -> int:
+        M, N, K = _shapes(A, B)
+        p = Problem(M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"), C.data_ptr(), _ld(C, "C"))
+        rid = ctypes.c_uint64()
+        check(lib().mm_serve_submit(self.handle, ctypes.byref(p), METHODS.get(method, method), arrival_s,
+                                    ctypes.byref(rid)))
+        return rid.value
+
+    def submit_raw(self, prob: Problem, method: int, arrival_s: float = -1.0) -> int:
+        rid = ctypes.c_uint64()
+        check(lib().mm_serve_submit(self.handle, ctypes.byref(prob), method, arrival_s, ctypes.byref(rid)))
+        return rid.value
+
+    def wait(self, rid: int, timeout_us: int = -1):
+        st, lat = ctypes.c_int(), ctypes.c_double()
+        check(lib().mm_serve_wait(self.handle, rid, timeout_us, ctypes.byref(st), ctypes.byref(lat)))
+        return st.value, lat.value
+
+    def stats(self) -> dict:
+        s = ServeStats()
+        check(lib().mm_serve_stats(self.handle, ctypes.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if self.handle:
+            check(lib().mm_serve_destroy(self.handle))
+            self.handle = ctypes.c_void_p(None)
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,247 @@
+// Tile-variant selection and the autotuner.
+//
+// The variant used for a product is a pure function of (method, shape bucket)
+// and the loaded cache: the bucket is (method, ceil(log2 M), ceil(log2 N),
+// ceil(log2 K)); a cache entry written by mm_autotune wins, otherwise a fixed
+// size rule applies.  Selection never depends on load or timing at call time,
+// so the same shape always runs the same kernel (results are reproducible
+// bit for bit, alone or inside a batch).
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+namespace {
+
+typedef std::tuple<int, int, int, int> Key;
+
+struct Entry {
+    int variant;
+    double ms;
+};
+
+std::mutex g_mu;
+std::map<Key, Entry> g_cache;
+
+int clog2(int64_t x) {
+    int l = 0;
+    while (((int64_t)1 << l) < x) ++l;
+    return l;
+}
+
+Key key_of(mm_method m, int64_t M, int64_t N, int64_t K) {
+    return Key((int)m, clog2(M), clog2(N), clog2(K));
+}
+
+int default_variant(mm_method method, int64_t M, int64_t N, int64_t K) {
+    (void)K;
+    const int64_t mn = M * N;
+    switch (method) {
+        case MM_F64:
+            // 256x128 (8 waves) for large products, 128x128 mid, 64x64 small
+            if (M >= 2048 && N >= 1024) return 2;
+            if (mn >= (int64_t)512 * 512) return 0;
+            return 1;
+        case MM_F32:
+            if (M >= 2048 && N >= 1024) return 2;
+            if (mn >= (int64_t)512 * 512) return 0;
+            return 1;
+        case MM_SPLIT_BF16_3:
+        case MM_SPLIT_BF16_6:
+            if (mn >= (int64_t)512 * 512) return 0;
+            return 1;
+    }
+    return 0;
+}
+
+const char *method_name(int m) {
+    switch (m) {
+        case MM_F64: return "f64";
+        case MM_F32: return "f32";
+        case MM_SPLIT_BF16_3: return "split3";
+        case MM_SPLIT_BF16_6: return "split6";
+    }
+    return "?";
+}
+
+}  // namespace
+
+int select_variant(mm_method method, int64_t M, int64_t N, int64_t K) {
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        auto it = g_cache.find(key_of(method, M, N, K));
+        if (it != g_cache.end()) return it->second.variant;
+    }
+    return default_variant(method, M, N, K);
+}
+
+}  // namespace mm
+
+using namespace mm;
+
+extern "C" {
+
+mm_status mm_autotune(mm_method method, int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
+                      int64_t ldb, void *C, int64_t ldc, int32_t warmup, int32_t reps, int32_t *variant_out,
+                      double *ms_out, void *stream) {
+    try {
+        if (warmup < 0 || reps < 1) return fail(MM_E_INVAL, "warmup >= 0 and reps >= 1 required");
+        if (M <= 0 || N <= 0 || K <= 0) return fail(MM_E_INVAL, "autotune needs a non-empty product");
+        const int nv = mm_variant_count(method);
+        if (nv <= 0) return fail(MM_E_INVAL, "unknown method");
+        hipStream_t st = (hipStream_t)stream;
+        void *ws = nullptr;
+        size_t ws_bytes = 0;
+        if (method == MM_SPLIT_BF16_3 || method == MM_SPLIT_BF16_6) {
+            ws_bytes = mm_split_workspace_bytes(M, N, K, method == MM_SPLIT_BF16_3 ? 3 : 6);
+            MM_HIP(hipMalloc(&ws, ws_bytes));
+        }
+        hipEvent_t e0, e1;
+        MM_HIP(hipEventCreate(&e0));
+        MM_HIP(hipEventCreate(&e1));
+        int best = -1;
+        double best_ms = 0;
+        mm_status status = MM_OK;
+        for (int v = 0; v < nv && status == MM_OK; ++v) {
+            std::vector<float> times;
+            for (int r = 0; r < warmup + reps && status == MM_OK; ++r) {
+                if (hipEventRecord(e0, st) != hipSuccess) { status = MM_E_DEVICE; break; }
+                status = mm_gemm_variant(method, v, M, N, K, A, lda, B, ldb, C, ldc, ws, ws_bytes, stream);
+                if (status != MM_OK) break;
+                if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                    status = MM_E_DEVICE;
+                    break;
+                }
+                float ms = 0;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (r >= warmup) times.push_back(ms);
+            }
+            if (status != MM_OK) break;
+            std::sort(times.begin(), times.end());
+            const double med = times[times.size() / 2];
+            if (best < 0 || med < best_ms) {
+                best = v;
+                best_ms = med;
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (ws) hipFree(ws);
+        if (status != MM_OK) return status;
+        {
+            std::lock_guard<std::mutex> lock(g_mu);
+            g_cache[key_of(method, M, N, K)] = Entry{best, best_ms};
+        }
+        if (variant_out) *variant_out = best;
+        if (ms_out) *ms_out = best_ms;
+        return MM_OK;
+    } catch (...) {
+        return fail(MM_E_DEVICE, "autotune failed");
+    }
+}
+
+mm_status mm_autotune_clear(void) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_cache.clear();
+    return MM_OK;
+}
+
+// File format (one JSON object):
+// {"arch": "gfx950", "version": "...", "entries": [[method, lm, ln, lk, variant, ms], ...]}
+mm_status mm_autotune_save(const char *path) {
+    try {
+        if (!path) return fail(MM_E_INVAL, "path is NULL");
+        std::ostringstream os;
+        os << "{\"arch\": \"gfx950\", \"version\": \"" << mm_version() << "\", \"entries\": [";
+        {
+            std::lock_guard<std::mutex> lock(g_mu);
+            bool first = true;
+            for (auto &kv : g_cache) {
+                if (!first) os << ", ";
+                first = false;
+                os << "[" << std::get<0>(kv.first) << ", " << std::get<1>(kv.first) << ", " << std::get<2>(kv.first)
+                   << ", " << std::get<3>(kv.first) << ", " << kv.second.variant << ", " << kv.second.ms << "]";
+            }
+        }
+        os << "]}\n";
+        std::string tmp = std::string(path) + ".tmp";
+        {
+            std::ofstream f(tmp);
+            if (!f) return fail(MM_E_INVAL, std::string("cannot write ") + tmp);
+            f << os.str();
+            if (!f) return fail(MM_E_INVAL, std::string("write failed: ") + tmp);
+        }
+        if (std::rename(tmp.c_str(), path) != 0) return fail(MM_E_INVAL, std::string("cannot rename to ") + path);
+        return MM_OK;
+    } catch (...) {
+        return fail(MM_E_DEVICE, "autotune save failed");
+    }
+}
+
+static bool find_string_field(const std::string &s, const char *name, std::string *out) {
+    const std::string pat = std::string("\"") + name + "\"";
+    size_t p = s.find(pat);
+    if (p == std::string::npos) return false;
+    p = s.find('"', s.find(':', p + pat.size()));
+    if (p == std::string::npos) return false;
+    size_t e = s.find('"', p + 1);
+    if (e == std::string::npos) return false;
+    *out = s.substr(p + 1, e - p - 1);
+    return true;
+}
+
+mm_status mm_autotune_load(const char *path) {
+    try {
+        if (!path) return fail(MM_E_INVAL, "path is NULL");
+        std::ifstream f(path);
+        if (!f) return fail(MM_E_INVAL, std::string("cannot read ") + path);
+        std::stringstream ss;
+        ss << f.rdbuf();
+        const std::string s = ss.str();
+        std::string arch, version;
+        if (!find_string_field(s, "arch", &arch) || arch != "gfx950")
+            return fail(MM_E_INVAL, "autotune cache is for another architecture");
+        if (!find_string_field(s, "version", &version) || version != mm_version())
+            return fail(MM_E_INVAL, "autotune cache is for another library version");
+        size_t p = s.find("\"entries\"");
+        if (p == std::string::npos) return fail(MM_E_INVAL, "no entries");
+        p = s.find('[', p);
+        if (p == std::string::npos) return fail(MM_E_INVAL, "malformed entries");
+        std::map<Key, Entry> fresh;
+        ++p;
+        while (true) {
+            size_t open = s.find('[', p);
+            size_t close_all = s.find(']', p);
+            if (open == std::string::npos || (close_all != std::string::npos && close_all < open)) break;
+            size_t close = s.find(']', open);
+            if (close == std::string::npos) return fail(MM_E_INVAL, "malformed entry");
+            double v[6];
+            if (std::sscanf(s.c_str() + open + 1, "%lf , %lf , %lf , %lf , %lf , %lf", &v[0], &v[1], &v[2], &v[3],
+                            &v[4], &v[5]) != 6)
+                return fail(MM_E_INVAL, "malformed entry");
+            const int method = (int)v[0], variant = (int)v[4];
+            if (method < 0 || method > 3 || variant < 0 || variant >= mm_variant_count((mm_method)method))
+                return fail(MM_E_INVAL, "entry names an unknown method or variant");
+            fresh[Key(method, (int)v[1], (int)v[2], (int)v[3])] = Entry{variant, v[5]};
+            p = close + 1;
+        }
+        std::lock_guard<std::mutex> lock(g_mu);
+        g_cache = fresh;
+        return MM_OK;
+    } catch (...) {
+        return fail(MM_E_DEVICE, "autotune load failed");
+    }
+}
+
+}  // extern "C"

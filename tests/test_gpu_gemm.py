@@ -1,0 +1,253 @@
+"""GPU parity of the single-problem entry points against the CPU oracle, on
+seeded inputs, through the C ABI (ctypes binding).  Bar: bit-exact on
+integer-valued inputs; otherwise |C - C_ref|_ij <= 4*K*u*(|A||B|)_ij with u the
+unit roundoff of the accumulation format; for the split form also the
+normwise error against the exact product."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_15384_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def mm():
+    from paper_2408_15384_amd import api
+    api.load_library()
+    assert api.lib().mm_init(0) == 0, api.lib().mm_last_error()
+    return api
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def assert_within_bound(C, A, B, u):
+    A64, B64 = np.asarray(A, np.float64), np.asarray(B, np.float64)
+    R = oracle.gemm(A64, B64)
+    bound = oracle.elementwise_bound(oracle.abs_product(A64, B64), A64.shape[1], u)
+    err = np.abs(np.asarray(C, np.float64) - R)
+    bad = err > bound
+    assert not bad.any(), f"{bad.sum()} entries outside the bound; worst ratio {(err / np.maximum(bound, 1e-300)).max()}"
+    return R
+
+
+RAGGED = [(1, 1, 1), (2, 3, 5), (15, 17, 31), (33, 63, 65), (127, 129, 255), (257, 130, 100), (300, 200, 513),
+          (64, 64, 64), (128, 256, 16)]
+
+
+@pytest.mark.parametrize("shape", RAGGED)
+def test_f64_ragged_uniform(mm, shape):
+    M, N, K = shape
+    A, B = I.pair("uniform_f64", M, N, K, seed=M * 7 + N)
+    C = host(mm.gemm_f64(dev(A), dev(B)))
+    assert_within_bound(C, A, B, oracle.U_F64)
+
+
+def test_f64_config_256_seed0(mm):
+    A, B = I.pair("uniform_f64", 256, 256, 256, seed=0)
+    C = host(mm.gemm_f64(dev(A), dev(B)))
+    assert_within_bound(C, A, B, oracle.U_F64)
+
+
+@pytest.mark.parametrize("n", [256, 1024])
+def test_f64_integer_bit_exact(mm, n):
+    A, B = I.pair("int_f64", n, n, n, seed=0)
+    C = host(mm.gemm_f64(dev(A), dev(B)))
+    assert np.array_equal(C, oracle.gemm(A, B))
+
+
+@pytest.mark.parametrize("method", ["f64", "f32"])
+def test_every_variant_ragged(mm, method):
+    M, N, K = 300, 270, 333
+    kind = "uniform_f64" if method == "f64" else "uniform_f32"
+    A, B = I.pair(kind, M, N, K, seed=3)
+    dA, dB = dev(A), dev(B)
+    u = oracle.U_F64 if method == "f64" else oracle.U_F32
+    outs = []
+    for v in range(mm.variant_count(method)):
+        C = torch.full((M, N), float("nan"), dtype=dA.dtype, device="cuda")
+        mm.gemm_variant(method, v, dA, dB, C)
+        Ch = host(C)
+        assert_within_bound(Ch, A, B, u)
+        outs.append(Ch)
+
+
+def test_f64_leading_dims_and_misaligned(mm):
+    M, N, K = 70, 45, 37
+    A, B = I.pair("uniform_f64", M, N, K, seed=4)
+    # padded leading dimensions (odd, so 16-byte vector loads are not allowed)
+    Ab = torch.zeros((M, K + 3), dtype=torch.float64, device="cuda")
+    Bb = torch.zeros((K, N + 5), dtype=torch.float64, device="cuda")
+    Cb = torch.full((M, N + 7), -7.0, dtype=torch.float64, device="cuda")
+    Ab[:, :K] = dev(A)
+    Bb[:, :N] = dev(B)
+    mm.gemm_f64(Ab[:, :K], Bb[:, :N], Cb[:, :N])
+    Ch = host(Cb)
+    assert_within_bound(Ch[:, :N], A, B, oracle.U_F64)
+    assert np.all(Ch[:, N:] == -7.0), "wrote outside C"
+    # misaligned base pointer (offset by one element)
+    flat = torch.zeros(M * K + 1, dtype=torch.float64, device="cuda")
+    flat[1:] = dev(A).reshape(-1)
+    Ch = host(mm.gemm_f64(flat[1:].view(M, K), dev(B)))
+    assert_within_bound(Ch, A, B, oracle.U_F64)
+
+
+def test_degenerate_sizes(mm):
+    A = torch.ones((5, 0), dtype=torch.float64, device="cuda")
+    B = torch.ones((0, 4), dtype=torch.float64, device="cuda")
+    C = torch.full((5, 4), 3.0, dtype=torch.float64, device="cuda")
+    mm.gemm_f64(A, B, C)
+    assert not host(C).any()            # K == 0 is the empty sum
+    E = mm.gemm_f64(torch.ones((0, 3), dtype=torch.float64, device="cuda"),
+                    torch.ones((3, 4), dtype=torch.float64, device="cuda"))
+    assert E.shape == (0, 4)
+    C32 = torch.full((5, 4), 3.0, dtype=torch.float32, device="cuda")
+    mm.gemm_f32(A.float(), B.float(), C32)
+    assert not host(C32).any()
+
+
+def test_invalid_arguments_rejected(mm):
+    lib = mm.lib()
+    A = torch.ones((4, 4), dtype=torch.float64, device="cuda")
+    p = A.data_ptr()
+    assert lib.mm_gemm_f64(-1, 4, 4, p, 4, p, 4, p, 4, None) == mm.MM_E_INVAL
+    assert lib.mm_gemm_f64(4, 4, 4, p, 3, p, 4, p + 4096, 4, None) == mm.MM_E_INVAL      # lda < K
+    assert lib.mm_gemm_f64(4, 4, 4, p, 4, p, 4, p, 4, None) == mm.MM_E_INVAL            # C overlaps A
+    assert lib.mm_gemm_f64(4, 4, 4, None, 4, p, 4, p + 4096, 4, None) == mm.MM_E_INVAL  # NULL A
+    assert lib.mm_gemm_split_bf16(4, 4, 4, p, 4, p, 4, p + 4096, 4, 0, 5, None, 0, None) == mm.MM_E_INVAL
+    assert b"nprod" in lib.mm_last_error()
+
+
+@pytest.mark.parametrize("shape", RAGGED)
+def test_f32_ragged_uniform(mm, shape):
+    M, N, K = shape
+    A, B = I.pair("uniform_f32", M, N, K, seed=M * 5 + K)
+    C = host(mm.gemm_f32(dev(A), dev(B)))
+    assert_within_bound(C, A, B, oracle.U_F32)
+
+
+def test_f32_integer_bit_exact(mm):
+    A, B = I.pair("int_f32", 512, 384, 640, seed=0)
+    C = host(mm.gemm_f32(dev(A), dev(B)))
+    assert np.array_equal(C.astype(np.float64), oracle.gemm(A, B))
+
+
+# ------------------------------------------------------------------ split form
+
+@pytest.mark.parametrize("nplanes", [1, 2, 3])
+@pytest.mark.parametrize("transpose", [False, True])
+def test_split_planes_bit_exact(mm, nplanes, transpose):
+    X = I.uniform_f32(I.rng_for(20), (67, 131)) * np.float32(3.7)
+    P = host(mm.split_bf16(dev(X), nplanes, transpose=transpose))
+    ref = oracle.split_planes(X, nplanes)
+    for p in range(nplanes):
+        r = (ref[p].view(np.uint32) >> 16).astype(np.uint16)
+        if transpose:
+            r = r.T
+        assert np.array_equal(P[p].view(np.uint16), r), f"plane {p}"
+
+
+@pytest.mark.parametrize("nprod", [3, 6])
+@pytest.mark.parametrize("shape", [(1, 1, 1), (17, 33, 65), (129, 127, 255), (256, 256, 256), (70, 300, 40)])
+def test_split_matches_emulation(mm, nprod, shape):
+    M, N, K = shape
+    A, B = I.pair("uniform_f32", M, N, K, seed=K)
+    C = host(mm.gemm_split_bf16(dev(A), dev(B), nprod=nprod, out_dtype=torch.float64))
+    E = oracle.split_product(A, B, nprod)
+    bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F32)
+    assert np.all(np.abs(C - E) <= bound)
+
+
+@pytest.mark.parametrize("kind", ["uniform_f32", "m2e_f32"])
+def test_split_normwise_error(mm, kind):
+    n = 512
+    A, B = I.pair(kind, n, n, n, seed=0)
+    R = oracle.gemm(A, B)
+    e6 = oracle.normwise_rel(host(mm.gemm_split_bf16(dev(A), dev(B), nprod=6, out_dtype=torch.float64)), R)
+    e3 = oracle.normwise_rel(host(mm.gemm_split_bf16(dev(A), dev(B), nprod=3, out_dtype=torch.float64)), R)
+    assert e6 <= 1e-6
+    if kind == "uniform_f32":
+        assert 1e-6 < e3 < 1e-5   # the 3-product form is not FP32-accurate on zero-mean data
+    else:
+        assert e3 <= 3e-6   # all-positive data: about 1e-6 at n = 512, falling as 1/sqrt(K)
+
+
+def test_split_integer_bit_exact(mm):
+    A, B = I.pair("int_f32", 200, 300, 400, seed=1)
+    R = oracle.gemm(A, B)
+    for nprod in (3, 6):
+        C = host(mm.gemm_split_bf16(dev(A), dev(B), nprod=nprod))
+        assert np.array_equal(C.astype(np.float64), R)
+
+
+def test_split_explicit_workspace_and_variants(mm):
+    M, N, K = 200, 190, 180
+    A, B = I.pair("uniform_f32", M, N, K, seed=2)
+    dA, dB = dev(A), dev(B)
+    E = oracle.split_product(A, B, 6)
+    bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F32) + 2.0 ** -24 * np.abs(E)
+    ws = torch.empty(mm.split_workspace_bytes(M, N, K, 6), dtype=torch.uint8, device="cuda")
+    C = host(mm.gemm_split_bf16(dA, dB, nprod=6, workspace=ws))
+    assert np.all(np.abs(C - E) <= bound)
+    for v in range(mm.variant_count("split6")):
+        C = torch.empty((M, N), dtype=torch.float32, device="cuda")
+        mm.gemm_variant("split6", v, dA, dB, C)
+        assert np.all(np.abs(host(C) - E) <= bound)
+
+
+# ------------------------------------------------------------------ residual
+
+def test_residual_exact_and_planted(mm):
+    M, N, K = 90, 70, 110
+    A, B = I.pair("int_f64", M, N, K, seed=5)
+    C = oracle.gemm(A, B)
+    x = I.integer(I.rng_for(6), (N,))
+    r2, z2 = host(mm.residual_f64(dev(A), dev(B), dev(C), dev(x)))
+    o_r2, o_z2 = oracle.freivalds(A, B, C, x)
+    assert r2 == 0.0 and o_r2 == 0.0 and z2 == o_z2
+    C2 = C.copy()
+    C2[11, 13] += 3.0
+    r2, _ = host(mm.residual_f64(dev(A), dev(B), dev(C2), dev(x)))
+    assert r2 == (3.0 * x[13]) ** 2
+
+
+def test_residual_float_inputs(mm):
+    M, N, K = 300, 257, 129
+    A, B = I.pair("uniform_f32", M, N, K, seed=7)
+    x = I.probe_vector(N)
+    dA, dB = dev(A), dev(B)
+    C = mm.gemm_split_bf16(dA, dB, nprod=6)
+    r2, z2 = host(mm.residual_f64(dA, dB, C, dev(x)))
+    o_r2, o_z2 = oracle.freivalds(A, B, host(C), x)
+    assert abs(z2 - o_z2) <= 1e-12 * o_z2
+    assert abs(np.sqrt(r2) - np.sqrt(o_r2)) <= 1e-9 * np.sqrt(o_z2)
+    assert np.sqrt(r2 / z2) < 1e-6
+
+
+# ------------------------------------------------------------------ full size
+
+@pytest.mark.parametrize("kind", ["uniform_f64", "int_f64"])
+def test_f64_8192_sampled(mm, kind):
+    n = 8192
+    A, B = I.pair(kind, n, n, n, seed=0)
+    C = host(mm.gemm_f64(dev(A), dev(B)))
+    rng = np.random.default_rng(99)
+    rows = np.concatenate([rng.integers(0, n, 1500), [0, n - 1, n - 1, 0]])
+    cols = np.concatenate([rng.integers(0, n, 1500), [0, n - 1, 0, n - 1]])
+    ref = oracle.gemm_entries(A, B, rows, cols)
+    got = C[rows, cols]
+    if kind == "int_f64":
+        assert np.array_equal(got, ref)
+    else:
+        absref = oracle.gemm_entries(np.abs(A), np.abs(B), rows, cols)
+        assert np.all(np.abs(got - ref) <= 4 * n * oracle.U_F64 * absref)
