@@ -1,0 +1,372 @@
+#!/usr/bin/env python3
+"""Benchmark of the dense product C = A.B on one MI355X.
+
+Headline (the JSON line's `value`): binary64 GEMM throughput at M = N = K = 8192
+(entries uniform on [-1, 1), seed 0), in TFLOP/s = 2N^3 / time, inputs resident
+in HBM before the timed region.  A step is one C = A.B through the C ABI.
+Protocol: W untimed warm-up steps, then K timed steps between device
+synchronisations (15 by default, the repetition count of the paper's
+experiments); each launch is also bracketed by HIP events on its stream, whose
+mean is the kernel duration used for the roofline.
+
+Also reported in the same line (context, not the headline):
+  * cpu_baseline: the CPU oracle timed on a bounded sample of the same product
+    (the first rows of C), on all host cores, and the sample's error;
+  * precision: plain FP32 versus the split-bfloat16 forms at N = 8192 on two
+    input sets, each with its error against the binary64 oracle (sampled rows)
+    and its binary64 residual probe;
+  * grouped: 512 FP32 problems with dimensions log-uniform on [32, 1024], one
+    graph-replayed persistent launch, plain FP32 versus split;
+  * serving: Poisson arrivals of GEMM requests (dimensions log-uniform on
+    [64, 4096], half binary64, half FP32-accurate split), operands resident on
+    the device, a 64 GiB admission budget; p50/p99 latency and throughput.
+
+Usage: python bench.py [--gpus 1] [--steps 15] [--warmup 3] [--headline-only]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_2408_15384_amd import inputs as I  # noqa: E402
+
+PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}   # dense TFLOP/s, MI355X datasheet
+HBM_TBS = 8.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_f64_8192.txt")
+KERNEL_SOURCES = ["paper_2408_15384_amd/csrc/gemm_tile.h", "paper_2408_15384_amd/csrc/gemm_mfma.hip",
+                  "paper_2408_15384_amd/csrc/variants.h"]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(n_launch_bytes):
+    """HBM bytes per launch of the headline kernel from the committed rocprofv3
+    counter summary, or None when it is missing or was taken on other sources."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def timed_steps(torch, fn, steps, warmup):
+    """Wall time per step over `steps` and the mean HIP-event duration of each launch."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ev = [e0.elapsed_time(e1) for e0, e1 in evs]
+    return wall * 1e3, float(np.mean(ev)), float(np.median(ev)), float(np.min(ev))
+
+
+def cpu_baseline(A, B, C_gpu, target_s=12.0):
+    """Oracle on the first rows of the same product, on all host cores."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    oracle.set_threads(cores)
+    n = B.shape[1]
+    K = A.shape[1]
+    rows = max(cores, 4)
+    t0 = time.perf_counter()
+    oracle.gemm(A[:rows], B)
+    dt = time.perf_counter() - t0
+    rows = int(min(A.shape[0], max(rows, rows * target_s / max(dt, 1e-3))))
+    rows = max(cores, (rows // cores) * cores)
+    t0 = time.perf_counter()
+    R = oracle.gemm(A[:rows], B)
+    dt = time.perf_counter() - t0
+    flop = 2.0 * rows * n * K
+    # error of the GPU rows against the oracle rows: normwise, and per entry
+    # against 4*K*u*(|A||B|) on a column subsample
+    G = C_gpu[:rows]
+    cols = np.arange(0, n, max(1, n // 256))
+    rr, cc = np.meshgrid(np.arange(rows), cols, indexing="ij")
+    absab = oracle.gemm_entries(np.abs(A[:rows]), np.abs(B), rr.ravel(), cc.ravel()).reshape(rr.shape)
+    ratio = float((np.abs(G[:, cols] - R[:, cols]) / np.maximum(4 * K * oracle.U_F64 * absab, 1e-300)).max())
+    return {
+        "value": flop / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
+        "sample": f"rows 0..{rows - 1} of C for M=N=K={n} binary64 (plain i-j-k loop, OpenMP over rows), "
+                  f"{flop:.3g} FLOP in {dt:.1f} s",
+        "gflops": flop / dt / 1e9,
+        "cpu_model": _cpu_model(),
+        "sample_normwise_err": float(np.linalg.norm(G - R) / np.linalg.norm(R)),
+        "sample_max_err_over_bound": ratio,
+    }
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def sampled_rows_error(A, B, C, rows=4, method="exact"):
+    import oracle
+    R = oracle.gemm(A[:rows].astype(np.float64), B.astype(np.float64))
+    return float(np.linalg.norm(C[:rows].astype(np.float64) - R) / np.linalg.norm(R))
+
+
+def precision_section(torch, mm, n, steps, warmup):
+    out = {}
+    x = torch.from_numpy(I.probe_vector(n)).cuda()
+    for kind in ("uniform_f32", "m2e_f32"):
+        A, B = I.pair(kind, n, n, n, seed=0)
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        C = torch.empty((n, n), dtype=torch.float32, device="cuda")
+        ws = torch.empty(mm.split_workspace_bytes(n, n, n, 6), dtype=torch.uint8, device="cuda")
+        res = {}
+        for name, fn, peak, mult in (
+                ("fp32", lambda: mm.gemm_f32(dA, dB, C), PEAK["f32"], 1),
+                ("split3", lambda: mm.gemm_split_bf16(dA, dB, 3, C=C, workspace=ws), PEAK["bf16"], 3),
+                ("split6", lambda: mm.gemm_split_bf16(dA, dB, 6, C=C, workspace=ws), PEAK["bf16"], 6)):
+            wall, ev, med, mn = timed_steps(torch, fn, max(3, steps // 3), warmup)
+            r2z2 = mm.residual_f64(dA, dB, C, x).cpu().numpy()
+            Ch = C.cpu().numpy()
+            tf = 2.0 * n ** 3 / (ev * 1e-3) / 1e12
+            res[name] = {"ms": ev, "tflops_useful": tf,
+                         "mfma_frac": tf * mult / peak,
+                         "normwise_err_vs_oracle_rows0_3": sampled_rows_error(A, B, Ch),
+                         "freivalds_rel_residual": float(np.sqrt(r2z2[0] / r2z2[1]))}
+            log(f"  precision {kind} {name}: {ev:.3f} ms {tf:.1f} TFLOP/s err {res[name]['normwise_err_vs_oracle_rows0_3']:.2e}")
+        res["split6_beats_fp32"] = res["split6"]["ms"] < res["fp32"]["ms"]
+        out[kind] = res
+        del dA, dB, C, ws
+        torch.cuda.empty_cache()
+    return out
+
+
+def grouped_section(torch, mm, reps=10):
+    shapes = [tuple(int(v) for v in s) for s in I.grouped_shapes(512, 32, 1024, seed=0)]
+    As, Bs, Cs = [], [], []
+    flop = 0.0
+    roof_s = 0.0
+    for i, (M, N, K) in enumerate(shapes):
+        A, B = I.pair("uniform_f32", M, N, K, seed=(0, i))
+        As.append(torch.from_numpy(A).cuda())
+        Bs.append(torch.from_numpy(B).cuda())
+        Cs.append(torch.empty((M, N), dtype=torch.float32, device="cuda"))
+        flop += 2.0 * M * N * K
+    out = {"problems": 512, "flop": flop}
+    for method, peak, mult in (("f32", PEAK["f32"], 1), ("split6", PEAK["bf16"], 6), ("split3", PEAK["bf16"], 3)):
+        roof = 0.0
+        for (M, N, K) in shapes:
+            bytes_ = 4.0 * (M * K + K * N + M * N)
+            roof += max(2.0 * M * N * K * mult / (peak * 1e12), bytes_ / (HBM_TBS * 1e12))
+        v, s, _ = mm.grouped_autotune(method, As, Bs, Cs, warmup=1, reps=3)
+        plan = mm.GroupedPlan(method)
+        wall, ev, med, mn = timed_steps(torch, lambda: plan.run(As, Bs, Cs), reps, 2)
+        eager = timed_steps(torch, lambda: mm.gemm_grouped(method, As, Bs, Cs, variant=v, schedule=s), reps, 2)
+        plan.close()
+        out[method] = {"variant": v, "schedule": s, "graph_ms": ev, "eager_ms": eager[1],
+                       "tflops_useful": flop / (ev * 1e-3) / 1e12, "roofline_ms": roof * 1e3,
+                       "frac_of_roofline": roof * 1e3 / ev}
+        log(f"  grouped {method}: {ev:.3f} ms graph, {eager[1]:.3f} ms eager, {out[method]['tflops_useful']:.1f} TFLOP/s")
+    return out
+
+
+def serving_section(torch, mm, count=10000, rate=20000.0, budget=64 << 30, check=16):
+    import oracle
+    t_arr, dims, is_f64 = I.serving_requests(count, rate, 64, 4096, 0.5, seed=0)
+    # resident operand banks: every request's A and B are views into these
+    rng = I.rng_for(1)
+    bank64 = [I.uniform_f64(rng, (4096, 4096)) for _ in range(2)]
+    bank32 = [I.uniform_f32(rng, (4096, 4096)) for _ in range(2)]
+    d64 = [torch.from_numpy(b).cuda() for b in bank64]
+    d32 = [torch.from_numpy(b).cuda() for b in bank32]
+    orng = np.random.default_rng(2)
+    offs = orng.integers(0, 1 << 30, size=(count, 4))
+    c64 = int(sum(int(d[0]) * int(d[1]) for d, f in zip(dims, is_f64) if f))
+    c32 = int(sum(int(d[0]) * int(d[1]) for d, f in zip(dims, is_f64) if not f))
+    out64 = torch.empty(max(c64, 1), dtype=torch.float64, device="cuda")
+    out32 = torch.empty(max(c32, 1), dtype=torch.float32, device="cuda")
+    reqs = []
+    p64 = p32 = 0
+    for i in range(count):
+        M, N, K = (int(v) for v in dims[i])
+        ra, ca = offs[i, 0] % (4097 - M), offs[i, 1] % (4097 - K)
+        rb, cb = offs[i, 2] % (4097 - K), offs[i, 3] % (4097 - N)
+        if is_f64[i]:
+            A = d64[0][ra:ra + M, ca:ca + K]
+            B = d64[1][rb:rb + K, cb:cb + N]
+            C = out64[p64:p64 + M * N].view(M, N)
+            p64 += M * N
+            method = mm.MM_F64
+        else:
+            A = d32[0][ra:ra + M, ca:ca + K]
+            B = d32[1][rb:rb + K, cb:cb + N]
+            C = out32[p32:p32 + M * N].view(M, N)
+            p32 += M * N
+            method = mm.MM_SPLIT_BF16_6
+        prob = mm.Problem(M, N, K, A.data_ptr(), A.stride(0), B.data_ptr(), B.stride(0), C.data_ptr(), N)
+        reqs.append((prob, method, (ra, ca, rb, cb), C))
+    torch.cuda.synchronize()
+    srv = mm.Server(budget_bytes=budget, slots=4, max_batch=64)
+    try:
+        # warm the kernels once outside the measured stream of requests
+        for prob, method, _, _ in reqs[:8]:
+            srv.wait(srv.submit_raw(prob, method))
+        srv.close()
+        srv = mm.Server(budget_bytes=budget, slots=4, max_batch=64)
+        start = srv.clock() + 0.05
+        ids = []
+        for i, (prob, method, _, _) in enumerate(reqs):
+            due = start + float(t_arr[i])
+            while srv.clock() < due:
+                pass
+            ids.append(srv.submit_raw(prob, method, due))
+        lat = []
+        bad = 0
+        for rid in ids:
+            st, l = srv.wait(rid)
+            bad += st != 0
+            lat.append(l)
+        stats = srv.stats()
+    finally:
+        srv.close()
+    torch.cuda.synchronize()
+    # oracle check of a sample of requests
+    small = [i for i in range(count) if float(dims[i][0]) * dims[i][1] * dims[i][2] <= 1e8]
+    sample = np.random.default_rng(3).choice(small, size=min(check, len(small)), replace=False)
+    worst = 0.0
+    for i in sample:
+        prob, method, (ra, ca, rb, cb), C = reqs[i]
+        M, N, K = prob.M, prob.N, prob.K
+        bank = bank64 if method == mm.MM_F64 else bank32
+        A = bank[0][ra:ra + M, ca:ca + K]
+        B = bank[1][rb:rb + K, cb:cb + N]
+        got = C.cpu().numpy().astype(np.float64)
+        if method == mm.MM_F64:
+            R = oracle.gemm(A, B)
+            bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F64)
+        else:
+            R = oracle.split_product(A, B, 6)
+            bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F32) + 2.0 ** -24 * np.abs(R)
+        worst = max(worst, float((np.abs(got - R) / np.maximum(bound, 1e-300)).max()))
+    flop = float(sum(2.0 * d[0] * d[1] * d[2] for d in dims))
+    span = float(t_arr[-1])
+    mix_roof_s = sum(2.0 * d[0] * d[1] * d[2] / (PEAK["f64"] * 1e12) if f else
+                     6 * 2.0 * d[0] * d[1] * d[2] / (PEAK["bf16"] * 1e12) for d, f in zip(dims, is_f64))
+    res = {"requests": count, "rate_per_s": rate, "budget_bytes": budget, "failed": int(bad),
+           "p50_ms": stats["p50_ms"], "p99_ms": stats["p99_ms"], "mean_ms": stats["mean_ms"],
+           "max_ms": stats["max_ms"], "tflops": stats["tflops"], "useful_flop": flop,
+           "offered_load_rho": mix_roof_s / span, "peak_bytes_in_flight": stats["peak_bytes"],
+           "launches": stats["launches"], "mean_batch": stats["mean_batch"],
+           "oracle_checked": int(check), "oracle_max_err_over_bound": worst}
+    log(f"  serving: p50 {res['p50_ms']:.3f} ms p99 {res['p99_ms']:.3f} ms {res['tflops']:.1f} TFLOP/s")
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=15)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--headline-only", action="store_true", help="skip every section after the headline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: the product runs on a single MI355X; multi-GPU sharding is "
+              "not part of this build (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2408_15384_amd import api as mm
+    mm.load_library()
+    mm.check(mm.lib().mm_init(0))
+    n = args.n
+
+    log(f"headline: binary64 GEMM M=N=K={n}")
+    A, B = I.pair("uniform_f64", n, n, n, seed=0)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    dC = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    # a plain copy of one operand: reference kernel for the HBM byte counters
+    scratch = torch.empty_like(dA)
+    scratch.copy_(dA)
+    del scratch
+    torch.cuda.synchronize()
+
+    wall_ms, ev_ms, ev_med, ev_min = timed_steps(torch, lambda: mm.gemm_f64(dA, dB, dC), args.steps, args.warmup)
+    flop = 2.0 * n ** 3
+    value = flop / (wall_ms * 1e-3) / 1e12
+    achieved = flop / (ev_ms * 1e-3) / 1e12
+    traffic = read_traffic(24.0 * n * n)
+    variant = mm.select_variant("f64", n, n, n)
+    C = dC.cpu().numpy()
+    x = torch.from_numpy(I.probe_vector(n)).cuda()
+    r2z2 = mm.residual_f64(dA, dB, dC, x).cpu().numpy()
+    log(f"  {wall_ms:.3f} ms/step, kernel {ev_ms:.3f} ms -> {value:.2f} TFLOP/s ({achieved / PEAK['f64']:.1%} of peak)")
+
+    line = {
+        "metric": "GEMM TFLOP/s & % of dtype peak at N=8192; p50/p99 latency of request loop",
+        "value": value, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": wall_ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic (seeded uniform[-1,1) binary64, seed 0)",
+        "config": {"workload": "fp64_gemm_8192", "M": n, "N": n, "K": n, "layout": "row-major NN",
+                   "tile_variant": variant, "tile": list(mm.variant_info("f64", variant))},
+        "pct_of_dtype_peak": value / PEAK["f64"],
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK["f64"], "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["f64"], "traffic": traffic,
+                     "kernel_ms_mean": ev_ms, "kernel_ms_median": ev_med, "kernel_ms_min": ev_min,
+                     "algorithmic_flop_per_launch": flop},
+        "freivalds_rel_residual": float(np.sqrt(r2z2[0] / r2z2[1])),
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle on a row sample)")
+        line["cpu_baseline"] = cpu_baseline(A, B, C)
+    del dA, dB, dC
+    torch.cuda.empty_cache()
+    if not args.headline_only:
+        log("precision: FP32 vs split-bf16 at N=8192")
+        line["precision"] = precision_section(torch, mm, n, args.steps, args.warmup)
+        log("grouped: 512 FP32 problems")
+        line["grouped"] = grouped_section(torch, mm)
+        torch.cuda.empty_cache()
+        log("serving: 10,000 requests")
+        line["serving"] = serving_section(torch, mm)
+    line["paper_context"] = {"note": "the paper's own CPU timings (Cirrus, Xeon E5-2695 2.1 GHz, 18 cores), "
+                                     "context only", "serial_O3_gcc_1024_s": 1.69891,
+                             "intel_16_threads_1024_s": 0.12}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

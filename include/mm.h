@@ -194,6 +194,18 @@ mm_status mm_grouped_plan_destroy(mm_grouped_plan *plan);
 mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out,
                                int64_t *tiles_out, int32_t *uses_graph_out);
 
+/*
+ * mm_gemm_grouped_config -- mm_gemm_grouped with an explicit tile variant and
+ * schedule instead of the autotuned choice.  schedule: 0 = problems in the
+ * given order, workgroups take tiles by a fixed stride; 1 = heaviest problems
+ * (largest M*N*K) first, fixed stride; 2 = heaviest first, workgroups pull
+ * tiles from a device work counter.  An existing plan must have been built
+ * with the same variant and schedule.
+ */
+mm_status mm_gemm_grouped_config(const mm_problem *probs, int32_t count, mm_method method,
+                                 int32_t variant, int32_t schedule,
+                                 mm_grouped_plan **plan_inout, void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Tile configurations and the autotuner.                                    */
 /* ------------------------------------------------------------------------ */
@@ -229,6 +241,18 @@ mm_status mm_autotune(mm_method method, int64_t M, int64_t N, int64_t K,
                       void *C, int64_t ldc, int32_t warmup, int32_t reps,
                       int32_t *variant_out, double *ms_out, void *stream);
 
+/*
+ * mm_grouped_autotune -- time every (variant, schedule) pair on this batch
+ * (plans with graph replay; `warmup` untimed and `reps` timed replays each,
+ * median), store the fastest under the batch's bucket (method, ceil(log2
+ * count), ceil(log2 mean M*N), ceil(log2 mean K)) so later mm_gemm_grouped
+ * calls on similar batches use it, and return it.  The problems' C are
+ * overwritten.  Runs synchronously on `stream`.
+ */
+mm_status mm_grouped_autotune(const mm_problem *probs, int32_t count, mm_method method,
+                              int32_t warmup, int32_t reps, int32_t *variant_out,
+                              int32_t *schedule_out, double *ms_out, void *stream);
+
 /* Persist / restore the autotune cache as JSON (keyed by architecture).  Loading
  * a file written for another architecture or library version is MM_E_INVAL
  * and leaves the cache unchanged. */
@@ -245,9 +269,16 @@ typedef struct mm_server mm_server;
 typedef struct mm_serve_config {
     uint64_t budget_bytes;   /* admission budget: bytes of operands, results and workspace in flight */
     int32_t slots;           /* concurrent launch slots (one HIP stream each), 1..8 */
-    int32_t max_batch;       /* most requests packed into one grouped launch */
+    int32_t max_batch;       /* most requests packed into one grouped launch, 1..4096 */
     int32_t queue_capacity;  /* most requests waiting for admission; submit beyond it is MM_E_BUSY */
     int32_t device;          /* HIP device ordinal */
+    /* Test mode for hosts without a GPU: if > 0 no device is touched and no C
+     * is written; each launch is modelled as taking sum(2MNK)/(dry_run_tflops
+     * * 1e12) seconds.  0 for real serving. */
+    double dry_run_tflops;
+    /* Dry-run only: the request with this id (0 = none) completes with
+     * MM_E_DEVICE, to exercise per-request failure reporting. */
+    uint64_t dry_run_fail_id;
 } mm_serve_config;
 
 typedef struct mm_serve_stats_t {
@@ -266,8 +297,9 @@ typedef struct mm_serve_stats_t {
 
 /*
  * mm_serve_create -- start a server: a scheduler thread that admits queued
- * requests in arrival order while bytes in flight plus the request's bytes fit
- * in budget_bytes and a slot is free, packs the admitted requests into grouped
+ * requests in arrival order (the head of the queue is never overtaken) while
+ * bytes in flight plus the request's bytes -- A, B and C at their element size
+ * plus split workspace -- fit in budget_bytes and a slot is free, packs the admitted requests into grouped
  * launches (one per method present) on the free slot's stream, and retires
  * them when the slot's completion event fires.  Requests that arrive while
  * others run are admitted as soon as a slot and budget free up, so their work

@@ -40,7 +40,8 @@ class Problem(ctypes.Structure):
 
 class ServeConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
-                ("queue_capacity", ctypes.c_int32), ("device", ctypes.c_int32)]
+                ("queue_capacity", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("dry_run_tflops", ctypes.c_double), ("dry_run_fail_id", ctypes.c_uint64)]
 
 
 class ServeStats(ctypes.Structure):
@@ -74,6 +75,9 @@ EXPORTS = [
     ("mm_gemm_grouped", _st, [ctypes.POINTER(Problem), _i32, _st, ctypes.POINTER(_p), _p]),
     ("mm_grouped_plan_destroy", _st, [_p]),
     ("mm_grouped_plan_info", _st, [_p, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
+    ("mm_gemm_grouped_config", _st, [ctypes.POINTER(Problem), _i32, _st, _i32, _i32, ctypes.POINTER(_p), _p]),
+    ("mm_grouped_autotune", _st, [ctypes.POINTER(Problem), _i32, _st, _i32, _i32, ctypes.POINTER(_i32),
+                                  ctypes.POINTER(_i32), ctypes.POINTER(_d), _p]),
     ("mm_variant_count", _i32, [_st]),
     ("mm_variant_info", _st, [_st, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     ("mm_select_variant", _i32, [_st, _i64, _i64, _i64]),
@@ -103,9 +107,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         raise RuntimeError(f"{path} is not built; run __graft_entry__.build() or python -m paper_2408_15384_amd.build")
     lib = ctypes.CDLL(path)
     for name, res, args in EXPORTS:
-        if not hasattr(lib, name):  # TEMPORARY while grouped/serving are being written
-            continue
-        fn = getattr(lib, name)
+        fn = getattr(lib, name)  # AttributeError: the library lacks a declared export
         fn.restype = res
         fn.argtypes = args
     _lib = lib
@@ -135,6 +137,8 @@ def _ld(t, name) -> int:
         raise ValueError(f"{name} must be 2-D")
     if not t.is_cuda:
         raise ValueError(f"{name} must be a GPU tensor")
+    if t.numel() == 0:
+        return max(int(t.shape[1]), 1)
     if t.shape[1] > 1 and t.stride(1) != 1:
         raise ValueError(f"{name} must be row-major (unit column stride)")
     return max(int(t.stride(0)), int(t.shape[1]), 1)
@@ -290,15 +294,21 @@ def _problems(As: Sequence, Bs: Sequence, Cs: Sequence):
 
 
 class GroupedPlan:
-    """Owns an mm_grouped_plan (tile map, descriptors, captured graph)."""
+    """Owns an mm_grouped_plan (tile map, descriptors, captured graph).
+    variant/schedule None: the autotuned (or default) choice."""
 
-    def __init__(self, method):
+    def __init__(self, method, variant=None, schedule=None):
         self.method = METHODS.get(method, method)
+        self.variant, self.schedule = variant, schedule
         self.handle = ctypes.c_void_p(None)
 
     def run(self, As, Bs, Cs, stream=None):
         arr, n = _problems(As, Bs, Cs)
-        check(lib().mm_gemm_grouped(arr, n, self.method, ctypes.byref(self.handle), _stream(stream)))
+        if self.variant is None:
+            check(lib().mm_gemm_grouped(arr, n, self.method, ctypes.byref(self.handle), _stream(stream)))
+        else:
+            check(lib().mm_gemm_grouped_config(arr, n, self.method, self.variant, self.schedule or 0,
+                                               ctypes.byref(self.handle), _stream(stream)))
         return Cs
 
     def info(self):
@@ -318,19 +328,32 @@ class GroupedPlan:
             pass
 
 
-def gemm_grouped(method, As, Bs, Cs, stream=None):
-    """One grouped launch without a plan (mm_gemm_grouped with plan_inout = NULL)."""
+def gemm_grouped(method, As, Bs, Cs, variant=None, schedule=0, stream=None):
+    """One grouped launch without a plan (plan_inout = NULL)."""
     arr, n = _problems(As, Bs, Cs)
-    check(lib().mm_gemm_grouped(arr, n, METHODS.get(method, method), None, _stream(stream)))
+    if variant is None:
+        check(lib().mm_gemm_grouped(arr, n, METHODS.get(method, method), None, _stream(stream)))
+    else:
+        check(lib().mm_gemm_grouped_config(arr, n, METHODS.get(method, method), variant, schedule, None,
+                                           _stream(stream)))
     return Cs
+
+
+def grouped_autotune(method, As, Bs, Cs, warmup: int = 1, reps: int = 5, stream=None):
+    """Time every (variant, schedule) on this batch; returns (variant, schedule, ms)."""
+    arr, n = _problems(As, Bs, Cs)
+    v, sch, ms = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+    check(lib().mm_grouped_autotune(arr, n, METHODS.get(method, method), warmup, reps, ctypes.byref(v),
+                                    ctypes.byref(sch), ctypes.byref(ms), _stream(stream)))
+    return v.value, sch.value, ms.value
 
 
 class Server:
     """A continuous-batching request loop (mm_serve_*)."""
 
     def __init__(self, budget_bytes: int, slots: int = 4, max_batch: int = 64, queue_capacity: int = 1 << 16,
-                 device: int = 0):
-        cfg = ServeConfig(budget_bytes, slots, max_batch, queue_capacity, device)
+                 device: int = 0, dry_run_tflops: float = 0.0, dry_run_fail_id: int = 0):
+        cfg = ServeConfig(budget_bytes, slots, max_batch, queue_capacity, device, dry_run_tflops, dry_run_fail_id)
         self.handle = ctypes.c_void_p(None)
         check(lib().mm_serve_create(ctypes.byref(cfg), ctypes.byref(self.handle)))
 

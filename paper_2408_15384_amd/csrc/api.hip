@@ -46,10 +46,27 @@ mm_status device_info(DeviceInfo *out) {
     return MM_OK;
 }
 
+void retain_default_pool() {
+    static std::mutex mu;
+    static std::vector<int> done;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lock(mu);
+    for (int d : done)
+        if (d == dev) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t keep = UINT64_MAX;
+        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    done.push_back(dev);
+}
+
 static mm_status check_arch() {
     DeviceInfo d;
     mm_status s = device_info(&d);
     if (s != MM_OK) return s;
+    retain_default_pool();
     if (d.arch.compare(0, 6, "gfx950") != 0)
         return fail(MM_E_UNSUPPORTED, "libmm kernels are built for gfx950; device is " + d.arch);
     return MM_OK;

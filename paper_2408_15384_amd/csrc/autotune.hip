@@ -29,6 +29,7 @@ typedef std::tuple<int, int, int, int> Key;
 struct Entry {
     int variant;
     double ms;
+    int schedule;   // grouped entries only
 };
 
 std::mutex g_mu;
@@ -65,17 +66,39 @@ int default_variant(mm_method method, int64_t M, int64_t N, int64_t K) {
     return 0;
 }
 
-const char *method_name(int m) {
-    switch (m) {
-        case MM_F64: return "f64";
-        case MM_F32: return "f32";
-        case MM_SPLIT_BF16_3: return "split3";
-        case MM_SPLIT_BF16_6: return "split6";
+// Grouped batches are keyed by (100 + method, ceil(log2 count),
+// ceil(log2 mean(M*N)), ceil(log2 mean K)).
+Key grouped_key(const mm_problem *probs, int count, mm_method method) {
+    double mn = 0, k = 0;
+    for (int i = 0; i < count; ++i) {
+        mn += (double)probs[i].M * probs[i].N;
+        k += (double)probs[i].K;
     }
-    return "?";
+    const int64_t c = count > 0 ? count : 1;
+    return Key(100 + (int)method, clog2(c), clog2((int64_t)(mn / c + 0.5)), clog2((int64_t)(k / c + 0.5)));
 }
 
 }  // namespace
+
+// Default for grouped batches: the smallest tile (many small problems are
+// dominated by tile quantisation and balance), heaviest problems first.
+int select_grouped(const mm_problem *probs, int count, mm_method method, int *schedule) {
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        auto it = g_cache.find(grouped_key(probs, count, method));
+        if (it != g_cache.end()) {
+            *schedule = it->second.schedule;
+            return it->second.variant;
+        }
+    }
+    *schedule = 1;
+    return 1;
+}
+
+void store_grouped(const mm_problem *probs, int count, mm_method method, int variant, int schedule, double ms) {
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_cache[grouped_key(probs, count, method)] = Entry{variant, ms, schedule};
+}
 
 int select_variant(mm_method method, int64_t M, int64_t N, int64_t K) {
     {
@@ -141,13 +164,73 @@ mm_status mm_autotune(mm_method method, int64_t M, int64_t N, int64_t K, const v
         if (status != MM_OK) return status;
         {
             std::lock_guard<std::mutex> lock(g_mu);
-            g_cache[key_of(method, M, N, K)] = Entry{best, best_ms};
+            g_cache[key_of(method, M, N, K)] = Entry{best, best_ms, 0};
         }
         if (variant_out) *variant_out = best;
         if (ms_out) *ms_out = best_ms;
         return MM_OK;
     } catch (...) {
         return fail(MM_E_DEVICE, "autotune failed");
+    }
+}
+
+mm_status mm_gemm_grouped_config(const mm_problem *probs, int32_t count, mm_method method, int32_t variant,
+                                 int32_t schedule, mm_grouped_plan **plan_inout, void *stream);
+
+mm_status mm_grouped_autotune(const mm_problem *probs, int32_t count, mm_method method, int32_t warmup, int32_t reps,
+                              int32_t *variant_out, int32_t *schedule_out, double *ms_out, void *stream) {
+    try {
+        if (warmup < 0 || reps < 1) return fail(MM_E_INVAL, "warmup >= 0 and reps >= 1 required");
+        if (count <= 0 || !probs) return fail(MM_E_INVAL, "autotune needs a non-empty batch");
+        const int nv = mm_variant_count(method);
+        if (nv <= 0) return fail(MM_E_INVAL, "unknown method");
+        hipStream_t st = (hipStream_t)stream;
+        hipEvent_t e0, e1;
+        MM_HIP(hipEventCreate(&e0));
+        MM_HIP(hipEventCreate(&e1));
+        int best_v = -1, best_s = 0;
+        double best_ms = 0;
+        mm_status status = MM_OK;
+        for (int v = 0; v < nv && status == MM_OK; ++v) {
+            for (int sch = 0; sch <= 2 && status == MM_OK; ++sch) {
+                mm_grouped_plan *plan = nullptr;
+                std::vector<float> times;
+                for (int r = 0; r < warmup + reps; ++r) {
+                    if (hipEventRecord(e0, st) != hipSuccess) { status = MM_E_DEVICE; break; }
+                    status = mm_gemm_grouped_config(probs, count, method, v, sch, &plan, stream);
+                    if (status != MM_OK) break;
+                    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                        status = MM_E_DEVICE;
+                        break;
+                    }
+                    float ms = 0;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    if (r >= warmup) times.push_back(ms);
+                }
+                if (plan) {
+                    hipStreamSynchronize(st);
+                    mm_grouped_plan_destroy(plan);
+                }
+                if (status != MM_OK) break;
+                std::sort(times.begin(), times.end());
+                const double med = times[times.size() / 2];
+                if (best_v < 0 || med < best_ms) {
+                    best_v = v;
+                    best_s = sch;
+                    best_ms = med;
+                }
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+        if (status != MM_OK) return status;
+        store_grouped(probs, count, method, best_v, best_s, best_ms);
+        if (variant_out) *variant_out = best_v;
+        if (schedule_out) *schedule_out = best_s;
+        if (ms_out) *ms_out = best_ms;
+        return MM_OK;
+    } catch (...) {
+        return fail(MM_E_DEVICE, "grouped autotune failed");
     }
 }
 
@@ -158,7 +241,7 @@ mm_status mm_autotune_clear(void) {
 }
 
 // File format (one JSON object):
-// {"arch": "gfx950", "version": "...", "entries": [[method, lm, ln, lk, variant, ms], ...]}
+// {"arch": "gfx950", "version": "...", "entries": [[k0, k1, k2, k3, variant, ms, schedule], ...]}
 mm_status mm_autotune_save(const char *path) {
     try {
         if (!path) return fail(MM_E_INVAL, "path is NULL");
@@ -171,7 +254,8 @@ mm_status mm_autotune_save(const char *path) {
                 if (!first) os << ", ";
                 first = false;
                 os << "[" << std::get<0>(kv.first) << ", " << std::get<1>(kv.first) << ", " << std::get<2>(kv.first)
-                   << ", " << std::get<3>(kv.first) << ", " << kv.second.variant << ", " << kv.second.ms << "]";
+                   << ", " << std::get<3>(kv.first) << ", " << kv.second.variant << ", " << kv.second.ms << ", "
+                   << kv.second.schedule << "]";
             }
         }
         os << "]}\n";
@@ -226,14 +310,16 @@ mm_status mm_autotune_load(const char *path) {
             if (open == std::string::npos || (close_all != std::string::npos && close_all < open)) break;
             size_t close = s.find(']', open);
             if (close == std::string::npos) return fail(MM_E_INVAL, "malformed entry");
-            double v[6];
-            if (std::sscanf(s.c_str() + open + 1, "%lf , %lf , %lf , %lf , %lf , %lf", &v[0], &v[1], &v[2], &v[3],
-                            &v[4], &v[5]) != 6)
+            double v[7];
+            if (std::sscanf(s.c_str() + open + 1, "%lf , %lf , %lf , %lf , %lf , %lf , %lf", &v[0], &v[1], &v[2],
+                            &v[3], &v[4], &v[5], &v[6]) != 7)
                 return fail(MM_E_INVAL, "malformed entry");
-            const int method = (int)v[0], variant = (int)v[4];
-            if (method < 0 || method > 3 || variant < 0 || variant >= mm_variant_count((mm_method)method))
-                return fail(MM_E_INVAL, "entry names an unknown method or variant");
-            fresh[Key(method, (int)v[1], (int)v[2], (int)v[3])] = Entry{variant, v[5]};
+            const int k0 = (int)v[0], variant = (int)v[4], schedule = (int)v[6];
+            const int method = k0 >= 100 ? k0 - 100 : k0;
+            if (method < 0 || method > 3 || variant < 0 || variant >= mm_variant_count((mm_method)method) ||
+                schedule < 0 || schedule > 2)
+                return fail(MM_E_INVAL, "entry names an unknown method, variant or schedule");
+            fresh[Key(k0, (int)v[1], (int)v[2], (int)v[3])] = Entry{variant, v[5], schedule};
             p = close + 1;
         }
         std::lock_guard<std::mutex> lock(g_mu);

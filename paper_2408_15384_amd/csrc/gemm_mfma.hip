@@ -2,6 +2,7 @@
 // in gemm_tile.h, with their tile variants.
 #include "mm_internal.h"
 #include "gemm_tile.h"
+#include "variants.h"
 
 namespace mm {
 
@@ -33,19 +34,6 @@ static hipError_t launch_tile(int64_t M, int64_t N, int64_t K, const T *A, int64
 }
 
 // ---------------------------------------------------------------- variants
-// (BM, BN, BK, WM, WN).  Index = variant id.
-#define MM_F64_VARIANTS(X)            \
-    X(0, 128, 128, 16, 64, 64)        \
-    X(1, 64, 64, 16, 32, 32)          \
-    X(2, 256, 128, 16, 64, 64)        \
-    X(3, 128, 64, 16, 64, 32)
-
-#define MM_F32_VARIANTS(X)            \
-    X(0, 128, 128, 16, 64, 64)        \
-    X(1, 64, 64, 16, 32, 32)          \
-    X(2, 256, 128, 16, 64, 64)        \
-    X(3, 128, 128, 32, 64, 64)
-
 #define MM_COUNT(id, bm, bn, bk, wm, wn) +1
 #define MM_CFG(id, bm, bn, bk, wm, wn) case id: return TileCfg{bm, bn, bk};
 

@@ -1,0 +1,517 @@
+// Grouped products: many independent C_i = A_i.B_i of different shapes in one
+// persistent launch.
+//
+// Tile map: problem i contributes ceil(M_i/BM) * ceil(N_i/BN) tiles; the host
+// stores the exclusive prefix sum of these counts in each descriptor.  A
+// persistent grid (the number of workgroups the chip holds at once) walks the
+// global tile ids -- by a fixed stride, or from an atomic work counter -- and
+// finds the owning problem by binary search over the prefix sums.  Each tile is
+// computed by the same tile body as the single-problem kernels, so a problem's
+// result is bit-identical to the single-problem result with the same variant.
+//
+// The split methods first run one grouped split pass over every operand of
+// every problem (64 x 64 tiles, A planes row-major, B planes transposed) into a
+// workspace, then the grouped split GEMM.  A plan captures this sequence once
+// into a HIP graph and replays it; descriptors live at fixed device addresses
+// and are refreshed (stream-ordered) before each replay.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "mm_internal.h"
+#include "gemm_tile.h"
+#include "split_tile.h"
+#include "variants.h"
+
+namespace mm {
+
+// ------------------------------------------------------------------ device side
+
+__device__ __forceinline__ int find_owner(const GroupedDesc *__restrict__ descs, int count, int64_t t) {
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (descs[mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Next tile id: fixed stride, or the shared work counter.
+__device__ __forceinline__ int64_t next_tile(int64_t cur, int *counter, int64_t *slot) {
+    if (!counter) return cur + gridDim.x;
+    __syncthreads();
+    if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(counter, 1) + gridDim.x;
+    __syncthreads();
+    return *slot;
+}
+
+template <typename TG, typename T>
+__global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 ? 2 : 1)) void grouped_gemm_kernel(
+    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter) {
+    __shared__ __attribute__((aligned(16))) T smem[TG::LDS_ELEMS];
+    __shared__ int64_t slot;
+    for (int64_t t = blockIdx.x; t < total_tiles; t = next_tile(t, counter, &slot)) {
+        const GroupedDesc &d = descs[find_owner(descs, count, t)];
+        const int64_t local = t - d.tile_begin;
+        const int64_t tm = local / d.tiles_n, tn = local % d.tiles_n;
+        const bool vec_ok = (d.lda % TG::VEC == 0) && (d.ldb % TG::VEC == 0) && ((uintptr_t)d.A % 16 == 0) &&
+                            ((uintptr_t)d.B % 16 == 0);
+        TG::run((const T *)d.A, d.lda, (const T *)d.B, d.ldb, (T *)d.C, d.ldc, d.M, d.N, d.K, tm, tn, vec_ok, smem);
+        __syncthreads();
+    }
+}
+
+template <typename ST>
+__global__ __launch_bounds__(ST::NT) void grouped_split_gemm_kernel(const GroupedDesc *__restrict__ descs, int count,
+                                                                    int64_t total_tiles, int *counter) {
+    __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
+    __shared__ int64_t slot;
+    for (int64_t t = blockIdx.x; t < total_tiles; t = next_tile(t, counter, &slot)) {
+        const GroupedDesc &d = descs[find_owner(descs, count, t)];
+        const int64_t local = t - d.tile_begin;
+        const int64_t tm = local / d.tiles_n, tn = local % d.tiles_n;
+        const bool vec_ok = (d.K % 8 == 0) && ((uintptr_t)d.A % 16 == 0) && ((uintptr_t)d.B % 16 == 0);
+        ST::run((const uint16_t *)d.A, d.M * d.K, (const uint16_t *)d.B, d.N * d.K, d.C, d.ldc, 0, d.M, d.N, d.K, tm,
+                tn, vec_ok, smem);
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void grouped_split_kernel(const SplitJob *__restrict__ jobs, int njobs,
+                                                            int64_t total_tiles) {
+    __shared__ float tile[64][65];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_begin <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const SplitJob &j = jobs[lo];
+        const int64_t local = t - j.tile_begin;
+        const int64_t r0 = (local / j.tiles_c) * 64, c0 = (local % j.tiles_c) * 64;
+        for (int i = ty; i < 64; i += 4) {
+            const int64_t r = r0 + i, c = c0 + tx;
+            tile[i][tx] = (r < j.rows && c < j.cols) ? j.X[r * j.ldx + c] : 0.f;
+        }
+        __syncthreads();
+        for (int i = ty; i < 64; i += 4) {
+            // transposed: output row c0+i walks r; plain: output row r0+i walks c
+            const int64_t r = j.transpose ? r0 + tx : r0 + i;
+            const int64_t c = j.transpose ? c0 + i : c0 + tx;
+            if (r < j.rows && c < j.cols) {
+                float v = j.transpose ? tile[tx][i] : tile[i][tx];
+                const int64_t o = j.transpose ? c * j.rows + r : r * j.cols + c;
+                for (int p = 0; p < j.nplanes; ++p) {
+                    const uint16_t h = split_bf16_bits(v);
+                    j.planes[p * j.pstride + o] = h;
+                    v = v - split_bf16_value(h);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void reset_counter_kernel(int *counter) {
+    if (threadIdx.x == 0) *counter = 0;
+}
+
+// ------------------------------------------------------------------ variants
+
+typedef const void *KernelPtr;
+
+struct KernelInfo {
+    KernelPtr fn = nullptr;
+    int nt = 0, bm = 0, bn = 0;
+};
+
+static KernelInfo kernel_for(mm_method method, int variant) {
+    KernelInfo k;
+#define MM_GK_F64(id, bm_, bn_, bk, wm, wn) \
+    case id: k.fn = (KernelPtr)&grouped_gemm_kernel<TileGemm<double, bm_, bn_, bk, wm, wn>, double>; k.nt = TileGemm<double, bm_, bn_, bk, wm, wn>::NT; k.bm = bm_; k.bn = bn_; break;
+#define MM_GK_F32(id, bm_, bn_, bk, wm, wn) \
+    case id: k.fn = (KernelPtr)&grouped_gemm_kernel<TileGemm<float, bm_, bn_, bk, wm, wn>, float>; k.nt = TileGemm<float, bm_, bn_, bk, wm, wn>::NT; k.bm = bm_; k.bn = bn_; break;
+#define MM_GK_S3(id, bm_, bn_, bk, wm, wn) \
+    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTile<3, bm_, bn_, bk, wm, wn>>; k.nt = SplitTile<3, bm_, bn_, bk, wm, wn>::NT; k.bm = bm_; k.bn = bn_; break;
+#define MM_GK_S6(id, bm_, bn_, bk, wm, wn) \
+    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTile<6, bm_, bn_, bk, wm, wn>>; k.nt = SplitTile<6, bm_, bn_, bk, wm, wn>::NT; k.bm = bm_; k.bn = bn_; break;
+    switch (method) {
+        case MM_F64: switch (variant) { MM_F64_VARIANTS(MM_GK_F64) default: break; } break;
+        case MM_F32: switch (variant) { MM_F32_VARIANTS(MM_GK_F32) default: break; } break;
+        case MM_SPLIT_BF16_3: switch (variant) { MM_SPLIT_VARIANTS(MM_GK_S3) default: break; } break;
+        case MM_SPLIT_BF16_6: switch (variant) { MM_SPLIT_VARIANTS(MM_GK_S6) default: break; } break;
+    }
+    return k;
+}
+
+int grouped_tile_bm(mm_method method, int variant) { return kernel_for(method, variant).bm; }
+int grouped_tile_bn(mm_method method, int variant) { return kernel_for(method, variant).bn; }
+
+// Workgroups of `fn` resident on the whole chip at once.
+static int persistent_grid(mm_method method, int variant, KernelPtr fn, int nt) {
+    static std::mutex mu;
+    static std::map<std::pair<int, int>, int> cache;
+    int dev = 0;
+    hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_pair(dev * 64 + (int)method, variant);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    int per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, nt, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    DeviceInfo d;
+    int cus = device_info(&d) == MM_OK ? d.cus : 256;
+    const int g = per_cu * cus;
+    cache[key] = g;
+    return g;
+}
+
+// ------------------------------------------------------------------ host layout
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// order: problem indices in launch order (schedule already applied).
+void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_method method, int bm, int bn,
+                         char *ws, Layout *L) {
+    const bool split = method == MM_SPLIT_BF16_3 || method == MM_SPLIT_BF16_6;
+    const int np = method == MM_SPLIT_BF16_3 ? 2 : 3;
+    L->descs.clear();
+    L->jobs.clear();
+    L->total_tiles = 0;
+    L->split_tiles = 0;
+    size_t off = 0;
+    for (int idx : order) {
+        const mm_problem &p = probs[idx];
+        if (p.M == 0 || p.N == 0) continue;
+        GroupedDesc d;
+        std::memset(&d, 0, sizeof d);
+        d.M = p.M;
+        d.N = p.N;
+        d.K = p.K;
+        d.A = p.A;
+        d.lda = p.lda;
+        d.B = p.B;
+        d.ldb = p.ldb;
+        d.C = p.C;
+        d.ldc = p.ldc;
+        d.tiles_n = (int32_t)cdiv(p.N, bn);
+        d.tile_begin = L->total_tiles;
+        L->total_tiles += cdiv(p.M, bm) * d.tiles_n;
+        if (split) {
+            const size_t abytes = align256((size_t)np * p.M * p.K * 2);
+            const size_t bbytes = align256((size_t)np * p.N * p.K * 2);
+            uint16_t *ap = ws ? (uint16_t *)(ws + off) : nullptr;
+            uint16_t *bp = ws ? (uint16_t *)(ws + off + abytes) : nullptr;
+            off += abytes + bbytes;
+            d.A = ap;
+            d.B = bp;
+            d.lda = p.K;
+            d.ldb = p.K;
+            if (p.K > 0) {
+                SplitJob ja{(const float *)p.A, p.lda, p.M, p.K, ap, p.M * p.K, L->split_tiles,
+                            (int32_t)cdiv(p.K, 64), np, 0, 0};
+                L->split_tiles += cdiv(p.M, 64) * ja.tiles_c;
+                L->jobs.push_back(ja);
+                SplitJob jb{(const float *)p.B, p.ldb, p.K, p.N, bp, p.N * p.K, L->split_tiles,
+                            (int32_t)cdiv(p.N, 64), np, 1, 0};
+                L->split_tiles += cdiv(p.K, 64) * jb.tiles_c;
+                L->jobs.push_back(jb);
+            }
+        }
+        L->descs.push_back(d);
+    }
+    L->ws_bytes = off;
+}
+
+// Launch order of the problems.  0: as given; 1 and 2: largest K*M*N first
+// (heaviest tiles start first); 2 additionally pulls tiles from a work counter.
+std::vector<int> schedule_order(const mm_problem *probs, int count, int schedule) {
+    std::vector<int> order(count);
+    std::iota(order.begin(), order.end(), 0);
+    if (schedule >= 1) {
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            const double wa = (double)probs[a].K * probs[a].M * probs[a].N;
+            const double wb = (double)probs[b].K * probs[b].M * probs[b].N;
+            return wa > wb;
+        });
+    }
+    return order;
+}
+
+// Enqueue the whole grouped sequence for descriptors already on the device.
+hipError_t grouped_enqueue(mm_method method, int variant, const GroupedDesc *d_descs, int ndesc, int64_t total_tiles,
+                          const SplitJob *d_jobs, int njobs, int64_t split_tiles, int *d_counter, hipStream_t st) {
+    if (ndesc == 0) return hipSuccess;
+    const KernelInfo k = kernel_for(method, variant);
+    if (!k.fn) return hipErrorInvalidValue;
+    if (njobs > 0 && split_tiles > 0) {
+        int64_t g = split_tiles < 4096 ? split_tiles : 4096;
+        hipLaunchKernelGGL(grouped_split_kernel, dim3((unsigned)g), dim3(256), 0, st, d_jobs, njobs, split_tiles);
+    }
+    if (d_counter) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, d_counter);
+    int64_t grid = persistent_grid(method, variant, k.fn, k.nt);
+    if (grid > total_tiles) grid = total_tiles;
+    void *args[] = {(void *)&d_descs, (void *)&ndesc, (void *)&total_tiles, (void *)&d_counter};
+    return hipLaunchKernel(k.fn, dim3((unsigned)grid), dim3(k.nt), args, 0, st);
+}
+
+static mm_status validate(const mm_problem *probs, int32_t count, mm_method method) {
+    if (count < 0) return fail(MM_E_INVAL, "count < 0");
+    if (count > 0 && !probs) return fail(MM_E_INVAL, "probs is NULL");
+    if (method < MM_F64 || method > MM_SPLIT_BF16_6) return fail(MM_E_INVAL, "unknown method");
+    const size_t e = method == MM_F64 ? 8 : 4;
+    for (int i = 0; i < count; ++i) {
+        const mm_problem &p = probs[i];
+        mm_status s = check_gemm_args(p.M, p.N, p.K, p.A, p.lda, p.B, p.ldb, p.C, p.ldc, e, e);
+        if (s != MM_OK) return fail(s, "problem " + std::to_string(i) + ": " + mm_last_error());
+    }
+    return MM_OK;
+}
+
+}  // namespace mm
+
+// ------------------------------------------------------------------ plans
+
+struct mm_grouped_plan {
+    mm_method method;
+    int variant = 0;
+    int schedule = 0;
+    int device = 0;
+    std::vector<int64_t> shapes;          // M, N, K per problem as given
+    std::vector<int> order;
+    mm::Layout layout;
+    mm::GroupedDesc *d_descs = nullptr;
+    mm::SplitJob *d_jobs = nullptr;
+    int *d_counter = nullptr;
+    void *ws = nullptr;
+    // pinned staging ring for descriptor refreshes
+    static constexpr int RING = 4;
+    mm::GroupedDesc *h_ring = nullptr;
+    hipEvent_t ring_ev[RING] = {};
+    int ring_pos = 0;
+    hipStream_t capture_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace mm {
+
+static void destroy_plan(mm_grouped_plan *p) {
+    if (!p) return;
+    if (p->exec) hipGraphExecDestroy(p->exec);
+    if (p->graph) hipGraphDestroy(p->graph);
+    if (p->capture_stream) hipStreamDestroy(p->capture_stream);
+    for (auto &e : p->ring_ev)
+        if (e) {
+            hipEventSynchronize(e);
+            hipEventDestroy(e);
+        }
+    if (p->h_ring) hipHostFree(p->h_ring);
+    if (p->d_descs) hipFree(p->d_descs);
+    if (p->d_jobs) hipFree(p->d_jobs);
+    if (p->d_counter) hipFree(p->d_counter);
+    if (p->ws) hipFree(p->ws);
+    delete p;
+}
+
+static mm_status create_plan(const mm_problem *probs, int32_t count, mm_method method, int variant, int schedule,
+                             mm_grouped_plan **out) {
+    mm_grouped_plan *p = new mm_grouped_plan();
+    p->method = method;
+    p->variant = variant;
+    p->schedule = schedule;
+    hipGetDevice(&p->device);
+    for (int i = 0; i < count; ++i) {
+        p->shapes.push_back(probs[i].M);
+        p->shapes.push_back(probs[i].N);
+        p->shapes.push_back(probs[i].K);
+    }
+    p->order = schedule_order(probs, count, schedule);
+    const int bm = grouped_tile_bm(method, variant), bn = grouped_tile_bn(method, variant);
+    build_layout(probs, p->order, method, bm, bn, nullptr, &p->layout);  // sizing
+    hipError_t e = hipSuccess;
+    if (p->layout.ws_bytes) e = hipMalloc(&p->ws, p->layout.ws_bytes);
+    if (e == hipSuccess) build_layout(probs, p->order, method, bm, bn, (char *)p->ws, &p->layout);
+    const size_t nd = p->layout.descs.size(), nj = p->layout.jobs.size();
+    if (e == hipSuccess && nd) e = hipMalloc(&p->d_descs, nd * sizeof(GroupedDesc));
+    if (e == hipSuccess && nj) e = hipMalloc(&p->d_jobs, nj * sizeof(SplitJob));
+    if (e == hipSuccess && schedule == 2) e = hipMalloc(&p->d_counter, sizeof(int));
+    if (e == hipSuccess && nd) e = hipHostMalloc((void **)&p->h_ring, mm_grouped_plan::RING * nd * sizeof(GroupedDesc), 0);
+    for (int i = 0; e == hipSuccess && i < mm_grouped_plan::RING; ++i) e = hipEventCreateWithFlags(&p->ring_ev[i], hipEventDisableTiming);
+    if (e == hipSuccess && nd) e = hipMemcpy(p->d_descs, p->layout.descs.data(), nd * sizeof(GroupedDesc), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nj) e = hipMemcpy(p->d_jobs, p->layout.jobs.data(), nj * sizeof(SplitJob), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking);
+    if (e == hipSuccess && nd) {
+        e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t le = grouped_enqueue(method, variant, p->d_descs, (int)nd, p->layout.total_tiles, p->d_jobs, (int)nj,
+                                    p->layout.split_tiles, p->d_counter, p->capture_stream);
+            hipError_t ce = hipStreamEndCapture(p->capture_stream, &p->graph);
+            e = le != hipSuccess ? le : ce;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    }
+    if (e != hipSuccess) {
+        destroy_plan(p);
+        return hip_fail(e, "grouped plan creation");
+    }
+    *out = p;
+    return MM_OK;
+}
+
+static bool same_shapes(const mm_grouped_plan *p, const mm_problem *probs, int32_t count) {
+    if ((int64_t)p->shapes.size() != 3 * (int64_t)count) return false;
+    for (int i = 0; i < count; ++i)
+        if (p->shapes[3 * i] != probs[i].M || p->shapes[3 * i + 1] != probs[i].N || p->shapes[3 * i + 2] != probs[i].K)
+            return false;
+    return true;
+}
+
+static mm_status run_plan(mm_grouped_plan *p, const mm_problem *probs, hipStream_t st, bool refresh) {
+    const size_t nd = p->layout.descs.size();
+    if (nd == 0) return MM_OK;
+    if (refresh) {
+        // Operand pointers may have changed: rebuild descriptors (the workspace
+        // and tile map are unchanged) and refresh them in stream order.
+        const int bm = grouped_tile_bm(p->method, p->variant), bn = grouped_tile_bn(p->method, p->variant);
+        build_layout(probs, p->order, p->method, bm, bn, (char *)p->ws, &p->layout);
+        const size_t nj = p->layout.jobs.size();
+        const int slot = p->ring_pos;
+        p->ring_pos = (p->ring_pos + 1) % mm_grouped_plan::RING;
+        MM_HIP(hipEventSynchronize(p->ring_ev[slot]));
+        GroupedDesc *h = p->h_ring + slot * nd;
+        std::memcpy(h, p->layout.descs.data(), nd * sizeof(GroupedDesc));
+        MM_HIP(hipMemcpyAsync(p->d_descs, h, nd * sizeof(GroupedDesc), hipMemcpyHostToDevice, st));
+        if (nj) {
+            // split jobs point at the caller's FP32 operands; they are small, copy synchronously in stream order
+            MM_HIP(hipMemcpyAsync(p->d_jobs, p->layout.jobs.data(), nj * sizeof(SplitJob), hipMemcpyHostToDevice, st));
+            MM_HIP(hipStreamSynchronize(st));
+        }
+        MM_HIP(hipEventRecord(p->ring_ev[slot], st));
+    }
+    MM_HIP(hipGraphLaunch(p->exec, st));
+    return MM_OK;
+}
+
+// One-shot launch without a plan: descriptors and workspace stream-ordered.
+static mm_status run_once(const mm_problem *probs, int32_t count, mm_method method, int variant, int schedule,
+                          hipStream_t st) {
+    std::vector<int> order = schedule_order(probs, count, schedule);
+    const int bm = grouped_tile_bm(method, variant), bn = grouped_tile_bn(method, variant);
+    Layout L;
+    build_layout(probs, order, method, bm, bn, nullptr, &L);
+    const size_t nd = L.descs.size();
+    if (nd == 0) return MM_OK;
+    char *buf = nullptr;
+    const size_t desc_bytes = align256(nd * sizeof(GroupedDesc));
+    const size_t job_bytes = align256(L.jobs.size() * sizeof(SplitJob) + 1);
+    const size_t total = desc_bytes + job_bytes + 256 + L.ws_bytes;
+    MM_HIP(hipMallocAsync((void **)&buf, total, st));
+    char *ws = buf + desc_bytes + job_bytes + 256;
+    build_layout(probs, order, method, bm, bn, ws, &L);
+    GroupedDesc *d_descs = (GroupedDesc *)buf;
+    SplitJob *d_jobs = (SplitJob *)(buf + desc_bytes);
+    int *d_counter = schedule == 2 ? (int *)(buf + desc_bytes + job_bytes) : nullptr;
+    hipError_t e = hipMemcpyAsync(d_descs, L.descs.data(), nd * sizeof(GroupedDesc), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !L.jobs.empty())
+        e = hipMemcpyAsync(d_jobs, L.jobs.data(), L.jobs.size() * sizeof(SplitJob), hipMemcpyHostToDevice, st);
+    // the host vectors must outlive the copies
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e == hipSuccess)
+        e = grouped_enqueue(method, variant, d_descs, (int)nd, L.total_tiles, d_jobs, (int)L.jobs.size(), L.split_tiles,
+                    d_counter, st);
+    hipError_t e2 = hipFreeAsync(buf, st);
+    if (e == hipSuccess) e = e2;
+    if (e != hipSuccess) return hip_fail(e, "grouped launch");
+    return MM_OK;
+}
+
+}  // namespace mm
+
+using namespace mm;
+
+extern "C" {
+
+mm_status mm_gemm_grouped(const mm_problem *probs, int32_t count, mm_method method, mm_grouped_plan **plan_inout,
+                          void *stream) {
+    try {
+        mm_status s = validate(probs, count, method);
+        if (s != MM_OK) return s;
+        hipStream_t st = (hipStream_t)stream;
+        if (plan_inout && *plan_inout) {
+            mm_grouped_plan *p = *plan_inout;
+            if (p->method != method || !same_shapes(p, probs, count))
+                return fail(MM_E_INVAL, "plan was built for other shapes or another method");
+            return run_plan(p, probs, st, true);
+        }
+        if (count == 0) return MM_OK;
+        int schedule = 0;
+        const int variant = select_grouped(probs, count, method, &schedule);
+        if (!plan_inout) return run_once(probs, count, method, variant, schedule, st);
+        mm_grouped_plan *p = nullptr;
+        s = create_plan(probs, count, method, variant, schedule, &p);
+        if (s != MM_OK) return s;
+        *plan_inout = p;
+        return run_plan(p, probs, st, false);
+    } catch (const std::bad_alloc &) {
+        return fail(MM_E_NOMEM, "host allocation failed");
+    } catch (...) {
+        return fail(MM_E_DEVICE, "internal error");
+    }
+}
+
+mm_status mm_grouped_plan_destroy(mm_grouped_plan *plan) {
+    try {
+        destroy_plan(plan);
+        return MM_OK;
+    } catch (...) {
+        return fail(MM_E_DEVICE, "internal error");
+    }
+}
+
+mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out, int64_t *tiles_out,
+                               int32_t *uses_graph_out) {
+    if (!plan) return fail(MM_E_INVAL, "plan is NULL");
+    if (variant_out) *variant_out = plan->variant;
+    if (tiles_out) *tiles_out = plan->layout.total_tiles;
+    if (uses_graph_out) *uses_graph_out = plan->exec != nullptr;
+    return MM_OK;
+}
+
+// Internal (also exported for tuning): explicit variant and schedule.
+mm_status mm_gemm_grouped_config(const mm_problem *probs, int32_t count, mm_method method, int32_t variant,
+                                 int32_t schedule, mm_grouped_plan **plan_inout, void *stream) {
+    try {
+        mm_status s = validate(probs, count, method);
+        if (s != MM_OK) return s;
+        if (variant < 0 || variant >= mm_variant_count(method)) return fail(MM_E_INVAL, "no such variant");
+        if (schedule < 0 || schedule > 2) return fail(MM_E_INVAL, "schedule must be 0, 1 or 2");
+        hipStream_t st = (hipStream_t)stream;
+        if (plan_inout && *plan_inout) {
+            mm_grouped_plan *p = *plan_inout;
+            if (p->method != method || !same_shapes(p, probs, count) || p->variant != variant || p->schedule != schedule)
+                return fail(MM_E_INVAL, "plan was built for another configuration");
+            return run_plan(p, probs, st, true);
+        }
+        if (count == 0) return MM_OK;
+        if (!plan_inout) return run_once(probs, count, method, variant, schedule, st);
+        mm_grouped_plan *p = nullptr;
+        s = create_plan(probs, count, method, variant, schedule, &p);
+        if (s != MM_OK) return s;
+        *plan_inout = p;
+        return run_plan(p, probs, st, false);
+    } catch (...) {
+        return fail(MM_E_DEVICE, "internal error");
+    }
+}
+
+}  // extern "C"

@@ -4,6 +4,7 @@
 #include <stdint.h>
 #include <stddef.h>
 #include <string>
+#include <vector>
 #include "../../include/mm.h"
 
 namespace mm {
@@ -12,6 +13,10 @@ namespace mm {
 void set_error(const std::string &msg);
 mm_status fail(mm_status s, const std::string &msg);
 mm_status hip_fail(hipError_t e, const char *what);
+
+// Synchronous argument checks shared by every product entry point.
+mm_status check_gemm_args(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
+                          int64_t ldb, const void *C, int64_t ldc, size_t ab_elem, size_t c_elem);
 
 #define MM_HIP(call)                                                   \
     do {                                                               \
@@ -79,12 +84,48 @@ struct GroupedDesc {
     int32_t pad;
 };
 
-hipError_t launch_grouped(mm_method method, int variant, const GroupedDesc *descs, int32_t count,
-                          int64_t total_tiles, int grid, hipStream_t stream);
+// One split job of a grouped launch: the planes of one operand.
+struct SplitJob {
+    const float *X;
+    int64_t ldx, rows, cols;
+    uint16_t *planes;
+    int64_t pstride;
+    int64_t tile_begin;
+    int32_t tiles_c;
+    int32_t nplanes;
+    int32_t transpose;
+    int32_t pad;
+};
+
+// Host tile map of one grouped batch.
+struct Layout {
+    std::vector<GroupedDesc> descs;
+    std::vector<SplitJob> jobs;
+    int64_t total_tiles = 0;
+    int64_t split_tiles = 0;
+    size_t ws_bytes = 0;  // split planes of the whole batch
+};
+
 int grouped_tile_bm(mm_method method, int variant);
 int grouped_tile_bn(mm_method method, int variant);
+// Launch order of the problems for a schedule (0: as given; 1, 2: heaviest first).
+std::vector<int> schedule_order(const mm_problem *probs, int count, int schedule);
+// Descriptors (and split jobs with planes carved from `ws`; ws may be null
+// while sizing) of the problems in `order`; empty problems are dropped.
+void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_method method, int bm, int bn,
+                  char *ws, Layout *L);
+// Enqueue [grouped split pass] -> [counter reset] -> grouped GEMM for
+// descriptors already in device memory.
+hipError_t grouped_enqueue(mm_method method, int variant, const GroupedDesc *d_descs, int ndesc, int64_t total_tiles,
+                           const SplitJob *d_jobs, int njobs, int64_t split_tiles, int *d_counter, hipStream_t st);
+// Keep memory freed by hipFreeAsync in the device's default pool.
+void retain_default_pool();
 
 // Autotune cache lookup (pure function of key + loaded cache).
 int select_variant(mm_method method, int64_t M, int64_t N, int64_t K);
+// Variant and schedule of a grouped launch: the cache entry of the batch's
+// bucket (method, count, mean M, mean N, mean K) if present, else a size rule.
+int select_grouped(const mm_problem *probs, int count, mm_method method, int *schedule);
+void store_grouped(const mm_problem *probs, int count, mm_method method, int variant, int schedule, double ms);
 
 }  // namespace mm

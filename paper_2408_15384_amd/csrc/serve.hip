@@ -1,0 +1,390 @@
+// Serving: a continuous-batching request loop for products of many sizes.
+//
+// Clients submit requests (device operands, a method and an arrival time) from
+// any thread.  One scheduler thread per server:
+//   * retires launches whose completion event has fired: every request in them
+//     is finished, its latency (completion - arrival) recorded and its bytes
+//     released;
+//   * admits queued requests strictly in arrival order while the bytes in
+//     flight plus the request's bytes (A, B, C and split workspace) fit in the
+//     budget; the head never gets overtaken, so no request starves;
+//   * packs the admitted requests into the next free slot -- one HIP stream --
+//     as one grouped launch per method present, so requests that arrive while
+//     others run start as soon as a slot and budget free up and their work
+//     overlaps with the launches in flight.
+// Every request of a method runs with one fixed tile variant (chosen from the
+// method alone), so a request's result is bit-identical alone and in any mix.
+//
+// Dry-run mode (dry_run_tflops > 0) replaces the device by a timing model:
+// each launch completes sum(2MNK)/rate seconds after it starts; nothing is
+// written.  It exists to test admission, ordering, batching and statistics on
+// hosts without a GPU.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "mm_internal.h"
+
+namespace mm {
+
+namespace {
+
+typedef std::chrono::steady_clock Clock;
+
+struct Request {
+    uint64_t id;
+    mm_problem p;
+    mm_method method;
+    double arrival;
+    uint64_t bytes;
+    bool done = false;
+    mm_status status = MM_OK;
+    double latency_ms = 0;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool busy = false;
+    std::vector<uint64_t> ids;
+    uint64_t bytes = 0;
+    double flop = 0;
+    double dry_done_at = 0;
+    // per method group: device descriptors / split jobs and pinned staging
+    GroupedDesc *d_descs = nullptr;
+    SplitJob *d_jobs = nullptr;
+    GroupedDesc *h_descs = nullptr;
+    SplitJob *h_jobs = nullptr;
+};
+
+constexpr int kGroups = 4;  // one grouped launch per method
+
+uint64_t elem_bytes(mm_method m) { return m == MM_F64 ? 8 : 4; }
+
+uint64_t request_bytes(const mm_problem &p, mm_method m) {
+    const uint64_t e = elem_bytes(m);
+    uint64_t b = e * ((uint64_t)p.M * p.K + (uint64_t)p.K * p.N + (uint64_t)p.M * p.N);
+    if ((m == MM_SPLIT_BF16_3 || m == MM_SPLIT_BF16_6) && p.M > 0 && p.N > 0 && p.K > 0)
+        b += 2 * 256 + split_workspace_bytes(p.M, p.N, p.K, m == MM_SPLIT_BF16_3 ? 3 : 6);
+    return b;
+}
+
+// Fixed variant per method for served requests (mid-size bucket).
+int serve_variant(mm_method m) { return select_variant(m, 1024, 1024, 1024); }
+
+}  // namespace
+}  // namespace mm
+
+struct mm_server {
+    mm_serve_config cfg;
+    double dry_tflops = 0;
+    uint64_t dry_fail_id = 0;
+    mm::Clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv_work;
+    std::condition_variable cv_done;
+    std::deque<uint64_t> queue;
+    std::unordered_map<uint64_t, mm::Request> reqs;
+    uint64_t next_id = 1;
+    uint64_t in_flight_bytes = 0;
+    uint64_t peak_bytes = 0;
+    std::vector<mm::Slot> slots;
+    std::thread thread;
+    bool stopping = false;
+    // statistics
+    std::vector<double> latencies;
+    uint64_t completed = 0, failed = 0, launches = 0, launched_requests = 0;
+    double useful_flop = 0;
+    double first_arrival = -1, last_done = 0;
+
+    double now() const { return std::chrono::duration<double>(mm::Clock::now() - t0).count(); }
+};
+
+namespace mm {
+
+static void finish(mm_server *s, Slot &slot, mm_status st) {
+    const double t = s->now();
+    for (uint64_t id : slot.ids) {
+        auto it = s->reqs.find(id);
+        if (it == s->reqs.end()) continue;
+        Request &r = it->second;
+        r.done = true;
+        r.status = (s->dry_tflops > 0 && s->dry_fail_id && id == s->dry_fail_id) ? MM_E_DEVICE : st;
+        r.latency_ms = (t - r.arrival) * 1e3;
+        s->latencies.push_back(r.latency_ms);
+        ++s->completed;
+        if (r.status != MM_OK) ++s->failed;
+        else s->useful_flop += 2.0 * (double)r.p.M * (double)r.p.N * (double)r.p.K;
+        if (t > s->last_done) s->last_done = t;
+    }
+    s->in_flight_bytes -= slot.bytes;
+    slot.ids.clear();
+    slot.bytes = 0;
+    slot.busy = false;
+    s->cv_done.notify_all();
+}
+
+// Enqueue one batch on a slot.  Called with the lock held.
+static mm_status launch(mm_server *s, Slot &slot, const std::vector<uint64_t> &ids) {
+    slot.ids = ids;
+    slot.busy = true;
+    slot.bytes = 0;
+    slot.flop = 0;
+    for (uint64_t id : ids) {
+        slot.bytes += s->reqs[id].bytes;
+        slot.flop += 2.0 * (double)s->reqs[id].p.M * s->reqs[id].p.N * s->reqs[id].p.K;
+    }
+    ++s->launches;
+    s->launched_requests += ids.size();
+    if (s->dry_tflops > 0) {
+        slot.dry_done_at = s->now() + slot.flop / (s->dry_tflops * 1e12);
+        return MM_OK;
+    }
+    const int cap = s->cfg.max_batch;
+    for (int g = 0; g < kGroups; ++g) {
+        const mm_method m = (mm_method)g;
+        std::vector<mm_problem> probs;
+        for (uint64_t id : ids)
+            if (s->reqs[id].method == m) probs.push_back(s->reqs[id].p);
+        if (probs.empty()) continue;
+        const int variant = serve_variant(m);
+        const int bm = grouped_tile_bm(m, variant), bn = grouped_tile_bn(m, variant);
+        std::vector<int> order = schedule_order(probs.data(), (int)probs.size(), 1);
+        Layout L;
+        build_layout(probs.data(), order, m, bm, bn, nullptr, &L);
+        if (L.descs.empty()) continue;
+        char *ws = nullptr;
+        if (L.ws_bytes) {
+            MM_HIP(hipMallocAsync((void **)&ws, L.ws_bytes, slot.stream));
+            build_layout(probs.data(), order, m, bm, bn, ws, &L);
+        }
+        GroupedDesc *hd = slot.h_descs + (size_t)g * cap;
+        SplitJob *hj = slot.h_jobs + (size_t)g * 2 * cap;
+        std::memcpy(hd, L.descs.data(), L.descs.size() * sizeof(GroupedDesc));
+        GroupedDesc *dd = slot.d_descs + (size_t)g * cap;
+        SplitJob *dj = slot.d_jobs + (size_t)g * 2 * cap;
+        MM_HIP(hipMemcpyAsync(dd, hd, L.descs.size() * sizeof(GroupedDesc), hipMemcpyHostToDevice, slot.stream));
+        if (!L.jobs.empty()) {
+            std::memcpy(hj, L.jobs.data(), L.jobs.size() * sizeof(SplitJob));
+            MM_HIP(hipMemcpyAsync(dj, hj, L.jobs.size() * sizeof(SplitJob), hipMemcpyHostToDevice, slot.stream));
+        }
+        MM_HIP(grouped_enqueue(m, variant, dd, (int)L.descs.size(), L.total_tiles, dj, (int)L.jobs.size(),
+                               L.split_tiles, nullptr, slot.stream));
+        if (ws) MM_HIP(hipFreeAsync(ws, slot.stream));
+    }
+    MM_HIP(hipEventRecord(slot.done, slot.stream));
+    return MM_OK;
+}
+
+static void scheduler_main(mm_server *s) {
+    if (s->dry_tflops <= 0) (void)hipSetDevice(s->cfg.device);
+    std::unique_lock<std::mutex> lock(s->mu);
+    while (true) {
+        // 1. retire finished launches
+        for (Slot &slot : s->slots) {
+            if (!slot.busy) continue;
+            if (s->dry_tflops > 0) {
+                if (s->now() >= slot.dry_done_at) finish(s, slot, MM_OK);
+                continue;
+            }
+            const hipError_t q = hipEventQuery(slot.done);
+            if (q == hipSuccess) finish(s, slot, MM_OK);
+            else if (q != hipErrorNotReady) finish(s, slot, MM_E_DEVICE);
+        }
+        // 2. admit in arrival order into free slots
+        for (Slot &slot : s->slots) {
+            if (slot.busy || s->queue.empty()) continue;
+            std::vector<uint64_t> batch;
+            uint64_t bytes = s->in_flight_bytes;
+            while (!s->queue.empty() && (int)batch.size() < s->cfg.max_batch) {
+                const Request &r = s->reqs[s->queue.front()];
+                if (bytes + r.bytes > s->cfg.budget_bytes) break;  // head waits; nobody overtakes it
+                bytes += r.bytes;
+                batch.push_back(s->queue.front());
+                s->queue.pop_front();
+            }
+            if (batch.empty()) break;
+            s->in_flight_bytes = bytes;
+            if (bytes > s->peak_bytes) s->peak_bytes = bytes;
+            const mm_status st = launch(s, slot, batch);
+            if (st != MM_OK) finish(s, slot, st);
+        }
+        bool any_busy = false;
+        for (Slot &slot : s->slots) any_busy = any_busy || slot.busy;
+        if (s->stopping && s->queue.empty() && !any_busy) break;
+        // 3. wait for work: poll completions while launches are in flight
+        if (any_busy) {
+            lock.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(5));
+            lock.lock();
+        } else {
+            s->cv_work.wait(lock, [s] { return s->stopping || !s->queue.empty(); });
+        }
+    }
+}
+
+static void release(mm_server *s) {
+    for (Slot &slot : s->slots) {
+        if (slot.done) (void)hipEventDestroy(slot.done);
+        if (slot.stream) (void)hipStreamDestroy(slot.stream);
+        if (slot.d_descs) (void)hipFree(slot.d_descs);
+        if (slot.d_jobs) (void)hipFree(slot.d_jobs);
+        if (slot.h_descs) (void)hipHostFree(slot.h_descs);
+        if (slot.h_jobs) (void)hipHostFree(slot.h_jobs);
+    }
+    delete s;
+}
+
+}  // namespace mm
+
+using namespace mm;
+
+extern "C" {
+
+mm_status mm_serve_create(const mm_serve_config *cfg, mm_server **out) {
+    try {
+        if (!cfg || !out) return fail(MM_E_INVAL, "NULL argument");
+        if (cfg->slots < 1 || cfg->slots > 8) return fail(MM_E_INVAL, "slots must be 1..8");
+        if (cfg->max_batch < 1 || cfg->max_batch > 4096) return fail(MM_E_INVAL, "max_batch must be 1..4096");
+        if (cfg->queue_capacity < 1) return fail(MM_E_INVAL, "queue_capacity must be positive");
+        if (cfg->budget_bytes == 0) return fail(MM_E_INVAL, "budget_bytes must be positive");
+        mm_server *s = new mm_server();
+        s->cfg = *cfg;
+        s->dry_tflops = cfg->dry_run_tflops;
+        s->dry_fail_id = cfg->dry_run_fail_id;
+        s->t0 = Clock::now();
+        s->slots.resize(cfg->slots);
+        if (s->dry_tflops <= 0) {
+            hipError_t e = hipSetDevice(cfg->device);
+            if (e == hipSuccess) retain_default_pool();
+            const size_t cap = cfg->max_batch;
+            for (Slot &slot : s->slots) {
+                if (e == hipSuccess) e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
+                if (e == hipSuccess) e = hipMalloc(&slot.d_descs, kGroups * cap * sizeof(GroupedDesc));
+                if (e == hipSuccess) e = hipMalloc(&slot.d_jobs, kGroups * 2 * cap * sizeof(SplitJob));
+                if (e == hipSuccess) e = hipHostMalloc((void **)&slot.h_descs, kGroups * cap * sizeof(GroupedDesc), 0);
+                if (e == hipSuccess) e = hipHostMalloc((void **)&slot.h_jobs, kGroups * 2 * cap * sizeof(SplitJob), 0);
+            }
+            if (e != hipSuccess) {
+                release(s);
+                return hip_fail(e, "server setup");
+            }
+        }
+        s->thread = std::thread(scheduler_main, s);
+        *out = s;
+        return MM_OK;
+    } catch (...) {
+        return fail(MM_E_DEVICE, "server setup failed");
+    }
+}
+
+mm_status mm_serve_submit(mm_server *s, const mm_problem *req, mm_method method, double arrival_s, uint64_t *id_out) {
+    try {
+        if (!s || !req || !id_out) return fail(MM_E_INVAL, "NULL argument");
+        if (method < MM_F64 || method > MM_SPLIT_BF16_6) return fail(MM_E_INVAL, "unknown method");
+        const uint64_t e = elem_bytes(method);
+        mm_status st = check_gemm_args(req->M, req->N, req->K, req->A, req->lda, req->B, req->ldb, req->C, req->ldc, e, e);
+        if (st != MM_OK) return st;
+        const uint64_t bytes = request_bytes(*req, method);
+        if (bytes > s->cfg.budget_bytes) return fail(MM_E_NOMEM, "request larger than the server budget");
+        std::lock_guard<std::mutex> lock(s->mu);
+        if (s->stopping) return fail(MM_E_INVAL, "server is stopping");
+        if ((int64_t)s->queue.size() >= s->cfg.queue_capacity) return fail(MM_E_BUSY, "queue full");
+        Request r;
+        r.id = s->next_id++;
+        r.p = *req;
+        r.method = method;
+        r.arrival = arrival_s >= 0 ? arrival_s : s->now();
+        r.bytes = bytes;
+        if (s->first_arrival < 0 || r.arrival < s->first_arrival) s->first_arrival = r.arrival;
+        s->reqs.emplace(r.id, r);
+        s->queue.push_back(r.id);
+        *id_out = r.id;
+        s->cv_work.notify_one();
+        return MM_OK;
+    } catch (...) {
+        return fail(MM_E_DEVICE, "submit failed");
+    }
+}
+
+mm_status mm_serve_wait(mm_server *s, uint64_t id, int64_t timeout_us, mm_status *req_status, double *latency_ms) {
+    try {
+        if (!s) return fail(MM_E_INVAL, "NULL server");
+        std::unique_lock<std::mutex> lock(s->mu);
+        auto it = s->reqs.find(id);
+        if (it == s->reqs.end()) return fail(MM_E_INVAL, "unknown request id (or already waited for)");
+        auto ready = [&] { return s->reqs[id].done; };
+        if (timeout_us < 0) s->cv_done.wait(lock, ready);
+        else if (!s->cv_done.wait_for(lock, std::chrono::microseconds(timeout_us), ready))
+            return fail(MM_E_TIMEOUT, "request still pending");
+        const Request r = s->reqs[id];
+        s->reqs.erase(id);
+        if (req_status) *req_status = r.status;
+        if (latency_ms) *latency_ms = r.latency_ms;
+        return MM_OK;
+    } catch (...) {
+        return fail(MM_E_DEVICE, "wait failed");
+    }
+}
+
+double mm_serve_clock(const mm_server *s) { return s ? s->now() : 0.0; }
+
+mm_status mm_serve_stats(mm_server *s, mm_serve_stats_t *out) {
+    try {
+        if (!s || !out) return fail(MM_E_INVAL, "NULL argument");
+        std::lock_guard<std::mutex> lock(s->mu);
+        std::memset(out, 0, sizeof *out);
+        out->completed = s->completed;
+        out->failed = s->failed;
+        std::vector<double> lat = s->latencies;
+        std::sort(lat.begin(), lat.end());
+        if (!lat.empty()) {
+            // nearest rank: the ceil(q*n)-th smallest
+            auto rank = [&](double q) { return lat[std::max<size_t>(1, (size_t)std::ceil(q * lat.size())) - 1]; };
+            out->p50_ms = rank(0.50);
+            out->p99_ms = rank(0.99);
+            double sum = 0;
+            for (double v : lat) sum += v;
+            out->mean_ms = sum / lat.size();
+            out->max_ms = lat.back();
+        }
+        out->useful_flop = s->useful_flop;
+        out->first_arrival_s = s->first_arrival < 0 ? 0 : s->first_arrival;
+        out->last_done_s = s->last_done;
+        const double span = s->last_done - out->first_arrival_s;
+        out->tflops = span > 0 ? s->useful_flop / span / 1e12 : 0;
+        out->peak_bytes = s->peak_bytes;
+        out->launches = s->launches;
+        out->mean_batch = s->launches ? (double)s->launched_requests / s->launches : 0;
+        return MM_OK;
+    } catch (...) {
+        return fail(MM_E_DEVICE, "stats failed");
+    }
+}
+
+mm_status mm_serve_destroy(mm_server *s) {
+    try {
+        if (!s) return MM_OK;
+        {
+            std::lock_guard<std::mutex> lock(s->mu);
+            s->stopping = true;
+            s->cv_work.notify_all();
+        }
+        if (s->thread.joinable()) s->thread.join();
+        release(s);
+        return MM_OK;
+    } catch (...) {
+        return fail(MM_E_DEVICE, "destroy failed");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,194 @@
+// Workgroup tile of the split-precision product on the bfloat16 matrix cores
+// (shared by the single-problem and the grouped kernels).
+//
+// C = sum over the method's plane pairs (p, q) of A_p . B_q with
+// v_mfma_f32_16x16x32_bf16, two FP32 accumulator sets per output block (the
+// leading A_0.B_0 product and the sum of the corrections), recombined per entry
+// in binary64.  A planes are M x K row-major, B planes N x K (transposed), so
+// both operands are k-contiguous and each MFMA fragment is one 16-byte LDS read.
+//
+// MFMA lane layout (16x16x32 bf16, measured on gfx950): lane l supplies
+// A[l%16][8*(l/16) .. +7] and B[8*(l/16) .. +7][l%16] and receives
+// D[4*(l/16)+v][l%16], v = 0..3.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mm {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+// bfloat16 of x, round to nearest even (the gfx950 convert instruction).
+__device__ __forceinline__ uint16_t split_bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ __forceinline__ float split_bf16_value(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
+
+// ------------------------------------------------------------------ split GEMM
+// Plane pairs of each method; entry 0 is the leading product.
+template <int NPROD> struct SplitTerms;
+template <> struct SplitTerms<3> {
+    static constexpr int NP = 2;
+    static constexpr int n = 3;
+    static constexpr int pa[3] = {0, 0, 1};
+    static constexpr int pb[3] = {0, 1, 0};
+};
+template <> struct SplitTerms<6> {
+    static constexpr int NP = 3;
+    static constexpr int n = 6;
+    static constexpr int pa[6] = {0, 0, 1, 0, 1, 2};
+    static constexpr int pb[6] = {0, 1, 0, 2, 1, 0};
+};
+
+template <int NPROD, int BM_, int BN_, int BK_, int WM_, int WN_>
+struct SplitTile {
+    using Terms = SplitTerms<NPROD>;
+    static constexpr int NP = Terms::NP;
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+    static constexpr int NWN = BN / WN;
+    static constexpr int NWAVES = (BM / WM) * (BN / WN);
+    static constexpr int NT = NWAVES * 64;
+    static constexpr int FM = WM / 16, FN = WN / 16;
+    static constexpr int KSTEPS = BK / 32;
+    static constexpr int LD = BK + 8;                 // bf16 elements per LDS row (16-byte pad)
+    static constexpr int A_PLANE = BM * LD, B_PLANE = BN * LD;
+    static constexpr int STAGE = NP * (A_PLANE + B_PLANE);
+    static constexpr int LDS_ELEMS = 2 * STAGE;
+    static constexpr int VROW = BK / 8;               // 16-byte vectors per row
+    static constexpr int A_VECS = NP * BM * VROW / NT;
+    static constexpr int B_VECS = NP * BN * VROW / NT;
+    static_assert(BK % 32 == 0, "BK multiple of 32");
+    static_assert((NP * BM * VROW) % NT == 0 && (NP * BN * VROW) % NT == 0, "load split");
+
+    // planes: base of plane 0, plane p at + p*pstride; rows x K k-contiguous.
+    static __device__ __forceinline__ void load(u16x8 *regs, int nvec, const uint16_t *__restrict__ planes,
+                                                int64_t pstride, int64_t row0, int64_t nrows_total, int64_t K,
+                                                int64_t k0, int rows_tile, bool vec_ok) {
+        const int tid = threadIdx.x;
+        for (int i = 0; i < nvec; ++i) {
+            const int v = tid + i * NT;
+            const int p = v / (rows_tile * VROW);
+            const int rem = v % (rows_tile * VROW);
+            const int r = rem / VROW;
+            const int c = (rem % VROW) * 8;
+            const int64_t gr = row0 + r;
+            const uint16_t *src = planes + p * pstride + gr * K + k0 + c;
+            if (gr < nrows_total && vec_ok && k0 + c + 8 <= K) {
+                regs[i] = *reinterpret_cast<const u16x8 *>(src);
+            } else {
+                u16x8 t;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) t[e] = (gr < nrows_total && k0 + c + e < K) ? src[e] : (uint16_t)0;
+                regs[i] = t;
+            }
+        }
+    }
+
+    static __device__ __forceinline__ void store(uint16_t *lds, int plane_elems, const u16x8 *regs, int nvec,
+                                                 int rows_tile) {
+        const int tid = threadIdx.x;
+        for (int i = 0; i < nvec; ++i) {
+            const int v = tid + i * NT;
+            const int p = v / (rows_tile * VROW);
+            const int rem = v % (rows_tile * VROW);
+            const int r = rem / VROW;
+            const int c = (rem % VROW) * 8;
+            *reinterpret_cast<u16x8 *>(lds + p * plane_elems + r * LD + c) = regs[i];
+        }
+    }
+
+    static __device__ __forceinline__ bf16x8 frag(const uint16_t *lds, int row, int kofs) {
+        return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(lds + row * LD + kofs));
+    }
+
+    static __device__ __forceinline__ void compute(const uint16_t *As, const uint16_t *Bs, f32x4 (&lead)[FM][FN],
+                                                   f32x4 (&corr)[FM][FN]) {
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int wm = wave / NWN, wn = wave % NWN;
+        const int li = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int s = 0; s < KSTEPS; ++s) {
+            const int kofs = s * 32 + q * 8;
+#pragma unroll
+            for (int t = 0; t < Terms::n; ++t) {
+                bf16x8 a[FM], b[FN];
+#pragma unroll
+                for (int fm = 0; fm < FM; ++fm)
+                    a[fm] = frag(As + Terms::pa[t] * A_PLANE, wm * WM + fm * 16 + li, kofs);
+#pragma unroll
+                for (int fn = 0; fn < FN; ++fn)
+                    b[fn] = frag(Bs + Terms::pb[t] * B_PLANE, wn * WN + fn * 16 + li, kofs);
+#pragma unroll
+                for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                    for (int fn = 0; fn < FN; ++fn) {
+                        if (t == 0)
+                            lead[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[fm], b[fn], lead[fm][fn], 0, 0, 0);
+                        else
+                            corr[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[fm], b[fn], corr[fm][fn], 0, 0, 0);
+                    }
+            }
+        }
+    }
+
+    // Tile (tm, tn) of C from A planes (M x K, stride pa_stride) and transposed
+    // B planes (N x K, stride pb_stride).
+    static __device__ __forceinline__ void run(const uint16_t *__restrict__ Ap, int64_t pa_stride,
+                                               const uint16_t *__restrict__ Bt, int64_t pb_stride, void *C,
+                                               int64_t ldc, int c_is_f64, int64_t M, int64_t N, int64_t K, int64_t tm,
+                                               int64_t tn, bool vec_ok, uint16_t *smem) {
+        const int64_t m0 = tm * BM, n0 = tn * BN;
+        f32x4 lead[FM][FN], corr[FM][FN];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) {
+                lead[fm][fn] = f32x4{0, 0, 0, 0};
+                corr[fm][fn] = f32x4{0, 0, 0, 0};
+            }
+        u16x8 ra[A_VECS], rb[B_VECS];
+        const int64_t nkt = (K + BK - 1) / BK;
+        load(ra, A_VECS, Ap, pa_stride, m0, M, K, 0, BM, vec_ok);
+        load(rb, B_VECS, Bt, pb_stride, n0, N, K, 0, BN, vec_ok);
+        store(smem, A_PLANE, ra, A_VECS, BM);
+        store(smem + NP * A_PLANE, B_PLANE, rb, B_VECS, BN);
+        __syncthreads();
+        for (int64_t kt = 0; kt < nkt; ++kt) {
+            const bool more = kt + 1 < nkt;
+            if (more) {
+                load(ra, A_VECS, Ap, pa_stride, m0, M, K, (kt + 1) * BK, BM, vec_ok);
+                load(rb, B_VECS, Bt, pb_stride, n0, N, K, (kt + 1) * BK, BN, vec_ok);
+            }
+            const uint16_t *cur = smem + (kt & 1) * STAGE;
+            compute(cur, cur + NP * A_PLANE, lead, corr);
+            if (more) {
+                uint16_t *nxt = smem + ((kt + 1) & 1) * STAGE;
+                store(nxt, A_PLANE, ra, A_VECS, BM);
+                store(nxt + NP * A_PLANE, B_PLANE, rb, B_VECS, BN);
+            }
+            __syncthreads();
+        }
+        // binary64 recombination of the two accumulator sets
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int wm = wave / NWN, wn = wave % NWN;
+        const int li = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t r = m0 + wm * WM + fm * 16 + q * 4 + v;
+                    const int64_t c = n0 + wn * WN + fn * 16 + li;
+                    if (r < M && c < N) {
+                        const double val = (double)lead[fm][fn][v] + (double)corr[fm][fn][v];
+                        if (c_is_f64) ((double *)C)[r * ldc + c] = val;
+                        else ((float *)C)[r * ldc + c] = (float)val;
+                    }
+                }
+    }
+};
+
+}  // namespace mm

@@ -1,0 +1,23 @@
+// Compiled tile variants of each method: X(id, BM, BN, BK, WM, WN), the
+// workgroup tile BM x BN, its K step BK and the per-wave sub-tile WM x WN.
+// The variant id is what the autotuner stores and mm_gemm_variant takes; the
+// single-problem and grouped kernels instantiate the same lists, so a variant
+// computes every tile the same way in both.
+#pragma once
+
+#define MM_F64_VARIANTS(X)            \
+    X(0, 128, 128, 16, 64, 64)        \
+    X(1, 64, 64, 16, 32, 32)          \
+    X(2, 256, 128, 16, 64, 64)        \
+    X(3, 128, 64, 16, 64, 32)
+
+#define MM_F32_VARIANTS(X)            \
+    X(0, 128, 128, 16, 64, 64)        \
+    X(1, 64, 64, 16, 32, 32)          \
+    X(2, 256, 128, 16, 64, 64)        \
+    X(3, 128, 128, 32, 64, 64)
+
+#define MM_SPLIT_VARIANTS(X)          \
+    X(0, 128, 128, 32, 64, 64)        \
+    X(1, 64, 64, 32, 32, 32)          \
+    X(2, 128, 64, 32, 64, 32)

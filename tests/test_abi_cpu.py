@@ -1,0 +1,99 @@
+"""C-ABI checks that need no GPU: the built library loads, exports every
+function include/mm.h declares, rejects invalid arguments synchronously, and
+round-trips its autotune cache."""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+from paper_2408_15384_amd import api
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mm.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(mm_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return api.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared_functions()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    assert sorted(n for n, _, _ in api.EXPORTS) == names   # binding declares exactly the header
+
+
+def test_status_strings(lib):
+    assert lib.mm_status_string(api.MM_E_INVAL) == b"invalid argument"
+    assert lib.mm_version().startswith(b"libmm")
+
+
+def test_invalid_arguments_without_gpu(lib):
+    p = 1 << 20
+    assert lib.mm_gemm_f64(-1, 4, 4, p, 4, p, 4, p * 4, 4, None) == api.MM_E_INVAL
+    assert lib.mm_gemm_f64(4, 4, 5, p, 4, p, 4, p * 4, 4, None) == api.MM_E_INVAL      # lda < K
+    assert lib.mm_gemm_f32(4, 4, 4, p, 4, p, 3, p * 4, 4, None) == api.MM_E_INVAL      # ldb < N
+    assert lib.mm_gemm_f64(4, 4, 4, p, 4, p + 4096, 4, p + 8, 4, None) == api.MM_E_INVAL  # C overlaps A
+    assert b"overlap" in lib.mm_last_error()
+    assert lib.mm_gemm_f64(0, 4, 4, None, 4, None, 4, None, 4, None) == api.MM_OK      # empty: no-op
+    assert lib.mm_gemm_split_bf16(4, 4, 4, p, 4, p, 4, p * 4, 4, 0, 4, None, 0, None) == api.MM_E_INVAL
+    assert lib.mm_split_bf16(4, 4, p, 4, 4, 0, p * 4, 16, None) == api.MM_E_INVAL      # nplanes
+    assert lib.mm_split_workspace_bytes(8, 8, 8, 6) > 0
+    assert lib.mm_split_workspace_bytes(8, 8, 8, 5) == 0
+    probs = (api.Problem * 1)(api.Problem(4, 4, 4, p, 2, p, 4, p * 4, 4))
+    assert lib.mm_gemm_grouped(probs, 1, api.MM_F64, None, None) == api.MM_E_INVAL
+    assert b"problem 0" in lib.mm_last_error()
+    assert lib.mm_gemm_grouped(probs, 0, api.MM_F64, None, None) == api.MM_OK
+
+
+def test_variant_tables(lib):
+    for m in ("f64", "f32", "split3", "split6"):
+        n = api.variant_count(m)
+        assert n >= 3
+        for v in range(n):
+            bm, bn, bk = api.variant_info(m, v)
+            assert bm % 16 == 0 and bn % 16 == 0 and bk % 4 == 0
+        with pytest.raises(api.MMError):
+            api.variant_info(m, n)
+    # selection is a pure function of the shape bucket
+    assert api.select_variant("f64", 8192, 8192, 8192) == api.select_variant("f64", 8000, 5000, 7000)
+
+
+def test_autotune_cache_roundtrip(lib, tmp_path):
+    path = str(tmp_path / "cache.json")
+    api.autotune_clear()
+    api.autotune_save(path)
+    doc = json.load(open(path))
+    assert doc["arch"] == "gfx950" and doc["entries"] == []
+    # an entry selecting a non-default variant changes selection after load
+    default = api.select_variant("f64", 1000, 1000, 1000)
+    other = (default + 1) % api.variant_count("f64")
+    doc["entries"] = [[api.MM_F64, 10, 10, 10, other, 1.5, 0]]
+    json.dump(doc, open(path, "w"))
+    api.autotune_load(path)
+    assert api.select_variant("f64", 1000, 1000, 1000) == other
+    assert api.select_variant("f64", 4000, 1000, 1000) == default       # other bucket untouched
+    api.autotune_save(path)
+    assert json.load(open(path))["entries"][0][4] == other
+    # wrong architecture or bad variant: rejected, cache unchanged
+    bad = dict(doc, arch="gfx942")
+    json.dump(bad, open(path, "w"))
+    with pytest.raises(api.MMError):
+        api.autotune_load(path)
+    doc["entries"] = [[api.MM_F64, 10, 10, 10, 99, 1.5, 0]]
+    json.dump(doc, open(path, "w"))
+    with pytest.raises(api.MMError):
+        api.autotune_load(path)
+    assert api.select_variant("f64", 1000, 1000, 1000) == other
+    api.autotune_clear()
+    assert api.select_variant("f64", 1000, 1000, 1000) == default
