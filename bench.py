@@ -21,7 +21,8 @@ Also reported in the same line (context, not the headline):
     [64, 4096], half binary64, half FP32-accurate split), operands resident on
     the device, a 64 GiB admission budget; p50/p99 latency and throughput.
 
-Usage: python bench.py [--gpus 1] [--steps 15] [--warmup 3] [--headline-only]
+Usage: python bench.py [--gpus 1] [--steps 15] [--warmup 3] [--sections precision,grouped,serving|none]
+                       [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -300,7 +301,8 @@ def main():
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--headline-only", action="store_true", help="skip every section after the headline")
+    ap.add_argument("--sections", default="precision,grouped,serving",
+                    help="comma list of sections to run after the headline (precision, grouped, serving, or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -354,12 +356,15 @@ def main():
         line["cpu_baseline"] = cpu_baseline(A, B, C)
     del dA, dB, dC
     torch.cuda.empty_cache()
-    if not args.headline_only:
+    sections = [x for x in args.sections.split(",") if x and x != "none"]
+    if "precision" in sections:
         log("precision: FP32 vs split-bf16 at N=8192")
         line["precision"] = precision_section(torch, mm, n, args.steps, args.warmup)
+    if "grouped" in sections:
         log("grouped: 512 FP32 problems")
         line["grouped"] = grouped_section(torch, mm)
         torch.cuda.empty_cache()
+    if "serving" in sections:
         log("serving: 10,000 requests")
         line["serving"] = serving_section(torch, mm)
     line["paper_context"] = {"note": "the paper's own CPU timings (Cirrus, Xeon E5-2695 2.1 GHz, 18 cores), "
