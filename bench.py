@@ -193,84 +193,119 @@ def grouped_section(torch, mm, reps=10):
             roof += max(2.0 * M * N * K * mult / (peak * 1e12), bytes_ / (HBM_TBS * 1e12))
         v, s, _ = mm.grouped_autotune(method, As, Bs, Cs, warmup=1, reps=3)
         plan = mm.GroupedPlan(method)
-        wall, ev, med, mn = timed_steps(torch, lambda: plan.run(As, Bs, Cs), reps, 2)
-        eager = timed_steps(torch, lambda: mm.gemm_grouped(method, As, Bs, Cs, variant=v, schedule=s), reps, 2)
+        plan.run(As, Bs, Cs)
+        wall, ev, med, mn = timed_steps(torch, plan.replay, reps, 2)
+        # one-shot launch with the same configuration, the problem array marshalled once
+        arr, cnt = mm._problems(As, Bs, Cs)
+        mid = mm.METHODS[method]
+        eager = timed_steps(torch, lambda: mm.check(mm.lib().mm_gemm_grouped_config(
+            arr, cnt, mid, v, s, None, mm._stream(None))), reps, 2)
+        info = plan.info()
         plan.close()
-        out[method] = {"variant": v, "schedule": s, "graph_ms": ev, "eager_ms": eager[1],
+        out[method] = {"variant": v, "schedule": s, "tiles": info["tiles"], "grid": info["grid"],
+                       "graph_ms": ev, "eager_ms": eager[1],
                        "tflops_useful": flop / (ev * 1e-3) / 1e12, "roofline_ms": roof * 1e3,
                        "frac_of_roofline": roof * 1e3 / ev}
         log(f"  grouped {method}: {ev:.3f} ms graph, {eager[1]:.3f} ms eager, {out[method]['tflops_useful']:.1f} TFLOP/s")
     return out
 
 
-def serving_section(torch, mm, count=10000, rate=20000.0, budget=64 << 30, check=16):
+class ServingWorkload:
+    """Request stream of the serving configuration with resident operands: every
+    request's A and B are views into seeded 4096 x 4096 operand banks (binary64
+    for FP64 requests, FP32 for split ones) at seeded offsets; C is per request."""
+
+    def __init__(self, torch, mm, count=10000, rate=20000.0, seed=0):
+        self.count, self.rate = count, rate
+        self.t_arr, self.dims, self.is_f64 = I.serving_requests(count, rate, 64, 4096, 0.5, seed=seed)
+        rng = I.rng_for(1)
+        self.bank64 = [I.uniform_f64(rng, (4096, 4096)) for _ in range(2)]
+        self.bank32 = [I.uniform_f32(rng, (4096, 4096)) for _ in range(2)]
+        self.d64 = [torch.from_numpy(b).cuda() for b in self.bank64]
+        self.d32 = [torch.from_numpy(b).cuda() for b in self.bank32]
+        offs = np.random.default_rng(2).integers(0, 1 << 30, size=(count, 4))
+        c64 = int(sum(int(d[0]) * int(d[1]) for d, f in zip(self.dims, self.is_f64) if f))
+        c32 = int(sum(int(d[0]) * int(d[1]) for d, f in zip(self.dims, self.is_f64) if not f))
+        self.out64 = torch.empty(max(c64, 1), dtype=torch.float64, device="cuda")
+        self.out32 = torch.empty(max(c32, 1), dtype=torch.float32, device="cuda")
+        self.reqs = []
+        p64 = p32 = 0
+        for i in range(count):
+            M, N, K = (int(v) for v in self.dims[i])
+            ra, ca = offs[i, 0] % (4097 - M), offs[i, 1] % (4097 - K)
+            rb, cb = offs[i, 2] % (4097 - K), offs[i, 3] % (4097 - N)
+            if self.is_f64[i]:
+                A, B = self.d64[0][ra:ra + M, ca:ca + K], self.d64[1][rb:rb + K, cb:cb + N]
+                C = self.out64[p64:p64 + M * N].view(M, N)
+                p64 += M * N
+                method = mm.MM_F64
+            else:
+                A, B = self.d32[0][ra:ra + M, ca:ca + K], self.d32[1][rb:rb + K, cb:cb + N]
+                C = self.out32[p32:p32 + M * N].view(M, N)
+                p32 += M * N
+                method = mm.MM_SPLIT_BF16_6
+            prob = mm.Problem(M, N, K, A.data_ptr(), A.stride(0), B.data_ptr(), B.stride(0), C.data_ptr(), N)
+            self.reqs.append((prob, method, (ra, ca, rb, cb), C, A, B))
+        torch.cuda.synchronize()
+
+    LARGE_MN = 1024 * 1024
+
+    def tune(self, mm, sample=48):
+        """Grouped autotuner on a sample batch of each (method, size class) of the
+        requests; returns (variants, variants_large)."""
+        out = ([-1, -1, -1, -1], [-1, -1, -1, -1])
+        for method in (mm.MM_F64, mm.MM_SPLIT_BF16_6):
+            for large in (False, True):
+                idx = [i for i in range(self.count) if self.reqs[i][1] == method and
+                       (self.reqs[i][0].M * self.reqs[i][0].N >= self.LARGE_MN) == large][:sample]
+                As = [self.reqs[i][4] for i in idx]
+                Bs = [self.reqs[i][5] for i in idx]
+                Cs = [self.reqs[i][3] for i in idx]
+                v, sch, ms = mm.grouped_autotune(method, As, Bs, Cs, warmup=1, reps=3)
+                out[int(large)][method] = v
+        return out
+
+
+def serving_section(torch, mm, wl=None, slots=4, max_batch=64, budget=64 << 30, variants=None, check=16):
     import oracle
-    t_arr, dims, is_f64 = I.serving_requests(count, rate, 64, 4096, 0.5, seed=0)
-    # resident operand banks: every request's A and B are views into these
-    rng = I.rng_for(1)
-    bank64 = [I.uniform_f64(rng, (4096, 4096)) for _ in range(2)]
-    bank32 = [I.uniform_f32(rng, (4096, 4096)) for _ in range(2)]
-    d64 = [torch.from_numpy(b).cuda() for b in bank64]
-    d32 = [torch.from_numpy(b).cuda() for b in bank32]
-    orng = np.random.default_rng(2)
-    offs = orng.integers(0, 1 << 30, size=(count, 4))
-    c64 = int(sum(int(d[0]) * int(d[1]) for d, f in zip(dims, is_f64) if f))
-    c32 = int(sum(int(d[0]) * int(d[1]) for d, f in zip(dims, is_f64) if not f))
-    out64 = torch.empty(max(c64, 1), dtype=torch.float64, device="cuda")
-    out32 = torch.empty(max(c32, 1), dtype=torch.float32, device="cuda")
-    reqs = []
-    p64 = p32 = 0
-    for i in range(count):
-        M, N, K = (int(v) for v in dims[i])
-        ra, ca = offs[i, 0] % (4097 - M), offs[i, 1] % (4097 - K)
-        rb, cb = offs[i, 2] % (4097 - K), offs[i, 3] % (4097 - N)
-        if is_f64[i]:
-            A = d64[0][ra:ra + M, ca:ca + K]
-            B = d64[1][rb:rb + K, cb:cb + N]
-            C = out64[p64:p64 + M * N].view(M, N)
-            p64 += M * N
-            method = mm.MM_F64
-        else:
-            A = d32[0][ra:ra + M, ca:ca + K]
-            B = d32[1][rb:rb + K, cb:cb + N]
-            C = out32[p32:p32 + M * N].view(M, N)
-            p32 += M * N
-            method = mm.MM_SPLIT_BF16_6
-        prob = mm.Problem(M, N, K, A.data_ptr(), A.stride(0), B.data_ptr(), B.stride(0), C.data_ptr(), N)
-        reqs.append((prob, method, (ra, ca, rb, cb), C))
-    torch.cuda.synchronize()
-    srv = mm.Server(budget_bytes=budget, slots=4, max_batch=64)
+    if wl is None:
+        wl = ServingWorkload(torch, mm)
+    if variants is None:
+        variants = wl.tune(mm)
+    small_v, large_v = variants
+    count = wl.count
+    kw = dict(budget_bytes=budget, slots=slots, max_batch=max_batch, variants=small_v, variants_large=large_v,
+              large_mn=wl.LARGE_MN)
+    srv = mm.Server(**kw)
     try:
         # warm the kernels once outside the measured stream of requests
-        for prob, method, _, _ in reqs[:8]:
+        for prob, method, *_ in wl.reqs[:8]:
             srv.wait(srv.submit_raw(prob, method))
         srv.close()
-        srv = mm.Server(budget_bytes=budget, slots=4, max_batch=64)
+        srv = mm.Server(**kw)
         start = srv.clock() + 0.05
         ids = []
-        for i, (prob, method, _, _) in enumerate(reqs):
-            due = start + float(t_arr[i])
+        for i, (prob, method, *_) in enumerate(wl.reqs):
+            due = start + float(wl.t_arr[i])
             while srv.clock() < due:
                 pass
             ids.append(srv.submit_raw(prob, method, due))
-        lat = []
         bad = 0
         for rid in ids:
-            st, l = srv.wait(rid)
+            st, _ = srv.wait(rid)
             bad += st != 0
-            lat.append(l)
         stats = srv.stats()
     finally:
         srv.close()
     torch.cuda.synchronize()
-    # oracle check of a sample of requests
-    small = [i for i in range(count) if float(dims[i][0]) * dims[i][1] * dims[i][2] <= 1e8]
-    sample = np.random.default_rng(3).choice(small, size=min(check, len(small)), replace=False)
+    # oracle check of a sample of the smaller requests
+    small = [i for i in range(count) if float(wl.dims[i][0]) * wl.dims[i][1] * wl.dims[i][2] <= 1e8]
+    sample = np.random.default_rng(3).choice(small, size=min(check, len(small)), replace=False) if check else []
     worst = 0.0
     for i in sample:
-        prob, method, (ra, ca, rb, cb), C = reqs[i]
+        prob, method, (ra, ca, rb, cb), C = wl.reqs[i][:4]
         M, N, K = prob.M, prob.N, prob.K
-        bank = bank64 if method == mm.MM_F64 else bank32
+        bank = wl.bank64 if method == mm.MM_F64 else wl.bank32
         A = bank[0][ra:ra + M, ca:ca + K]
         B = bank[1][rb:rb + K, cb:cb + N]
         got = C.cpu().numpy().astype(np.float64)
@@ -281,17 +316,20 @@ def serving_section(torch, mm, count=10000, rate=20000.0, budget=64 << 30, check
             R = oracle.split_product(A, B, 6)
             bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F32) + 2.0 ** -24 * np.abs(R)
         worst = max(worst, float((np.abs(got - R) / np.maximum(bound, 1e-300)).max()))
-    flop = float(sum(2.0 * d[0] * d[1] * d[2] for d in dims))
-    span = float(t_arr[-1])
+    flop = float(sum(2.0 * d[0] * d[1] * d[2] for d in wl.dims))
+    span = float(wl.t_arr[-1])
     mix_roof_s = sum(2.0 * d[0] * d[1] * d[2] / (PEAK["f64"] * 1e12) if f else
-                     6 * 2.0 * d[0] * d[1] * d[2] / (PEAK["bf16"] * 1e12) for d, f in zip(dims, is_f64))
-    res = {"requests": count, "rate_per_s": rate, "budget_bytes": budget, "failed": int(bad),
+                     6 * 2.0 * d[0] * d[1] * d[2] / (PEAK["bf16"] * 1e12) for d, f in zip(wl.dims, wl.is_f64))
+    res = {"requests": count, "rate_per_s": wl.rate, "budget_bytes": budget, "slots": slots,
+           "max_batch": max_batch, "large_mn": wl.LARGE_MN,
+           "variants": {"f64": [small_v[0], large_v[0]], "split6": [small_v[3], large_v[3]]}, "failed": int(bad),
            "p50_ms": stats["p50_ms"], "p99_ms": stats["p99_ms"], "mean_ms": stats["mean_ms"],
            "max_ms": stats["max_ms"], "tflops": stats["tflops"], "useful_flop": flop,
            "offered_load_rho": mix_roof_s / span, "peak_bytes_in_flight": stats["peak_bytes"],
            "launches": stats["launches"], "mean_batch": stats["mean_batch"],
-           "oracle_checked": int(check), "oracle_max_err_over_bound": worst}
-    log(f"  serving: p50 {res['p50_ms']:.3f} ms p99 {res['p99_ms']:.3f} ms {res['tflops']:.1f} TFLOP/s")
+           "oracle_checked": len(sample), "oracle_max_err_over_bound": worst}
+    log(f"  serving slots={slots} batch={max_batch} v={variants}: p50 {res['p50_ms']:.3f} ms "
+        f"p99 {res['p99_ms']:.3f} ms {res['tflops']:.1f} TFLOP/s, {res['launches']} launches")
     return res
 
 

@@ -190,9 +190,16 @@ mm_status mm_gemm_grouped(const mm_problem *probs, int32_t count, mm_method meth
                           mm_grouped_plan **plan_inout, void *stream);
 mm_status mm_grouped_plan_destroy(mm_grouped_plan *plan);
 
-/* Tile configuration the plan chose (autotuned or default) and its tile count. */
-mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out,
-                               int64_t *tiles_out, int32_t *uses_graph_out);
+/* Replay a plan's graph on `stream` with the operands it last ran with (no
+ * descriptor refresh, one launch call).  The caller keeps those operands alive
+ * and unchanged in place; their contents may change between replays. */
+mm_status mm_grouped_plan_launch(mm_grouped_plan *plan, void *stream);
+
+/* Tile configuration the plan chose (autotuned or default), its schedule, its
+ * tile count, the workgroups of its persistent grid and whether it replays a
+ * graph.  Every output is nullable. */
+mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out, int32_t *schedule_out,
+                               int64_t *tiles_out, int32_t *grid_out, int32_t *uses_graph_out);
 
 /*
  * mm_gemm_grouped_config -- mm_gemm_grouped with an explicit tile variant and
@@ -279,6 +286,15 @@ typedef struct mm_serve_config {
     /* Dry-run only: the request with this id (0 = none) completes with
      * MM_E_DEVICE, to exercise per-request failure reporting. */
     uint64_t dry_run_fail_id;
+    /* Requests fall in two size classes by their own shape: "large" if
+     * M*N >= large_mn (0: 1024*1024), else "small"; each class of each method
+     * is launched as its own grouped launch with its own tile variant, so a
+     * request always runs with the same kernel.  variants[m] / variants_large[m]
+     * (index = mm_method) are the tile variants, e.g. from mm_grouped_autotune on
+     * a sample of the expected requests; -1 = the library's choice. */
+    int32_t variants[4];
+    int32_t variants_large[4];
+    int64_t large_mn;
 } mm_serve_config;
 
 typedef struct mm_serve_stats_t {

@@ -41,7 +41,9 @@ class Problem(ctypes.Structure):
 class ServeConfig(ctypes.Structure):
     _fields_ = [("budget_bytes", ctypes.c_uint64), ("slots", ctypes.c_int32), ("max_batch", ctypes.c_int32),
                 ("queue_capacity", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("dry_run_tflops", ctypes.c_double), ("dry_run_fail_id", ctypes.c_uint64)]
+                ("dry_run_tflops", ctypes.c_double), ("dry_run_fail_id", ctypes.c_uint64),
+                ("variants", ctypes.c_int32 * 4), ("variants_large", ctypes.c_int32 * 4),
+                ("large_mn", ctypes.c_int64)]
 
 
 class ServeStats(ctypes.Structure):
@@ -74,7 +76,9 @@ EXPORTS = [
     ("mm_residual_f64", _st, [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i32, _i32, _p, _p, _p, _sz, _p]),
     ("mm_gemm_grouped", _st, [ctypes.POINTER(Problem), _i32, _st, ctypes.POINTER(_p), _p]),
     ("mm_grouped_plan_destroy", _st, [_p]),
-    ("mm_grouped_plan_info", _st, [_p, ctypes.POINTER(_i32), ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
+    ("mm_grouped_plan_launch", _st, [_p, _p]),
+    ("mm_grouped_plan_info", _st, [_p, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i64),
+                                   ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     ("mm_gemm_grouped_config", _st, [ctypes.POINTER(Problem), _i32, _st, _i32, _i32, ctypes.POINTER(_p), _p]),
     ("mm_grouped_autotune", _st, [ctypes.POINTER(Problem), _i32, _st, _i32, _i32, ctypes.POINTER(_i32),
                                   ctypes.POINTER(_i32), ctypes.POINTER(_d), _p]),
@@ -311,10 +315,15 @@ class GroupedPlan:
                                                ctypes.byref(self.handle), _stream(stream)))
         return Cs
 
+    def replay(self, stream=None):
+        """Replay the captured graph with the operands of the last run."""
+        check(lib().mm_grouped_plan_launch(self.handle, _stream(stream)))
+
     def info(self):
-        v, t, g = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
-        check(lib().mm_grouped_plan_info(self.handle, ctypes.byref(v), ctypes.byref(t), ctypes.byref(g)))
-        return {"variant": v.value, "tiles": t.value, "graph": bool(g.value)}
+        v, s, t, grid, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib().mm_grouped_plan_info(self.handle, ctypes.byref(v), ctypes.byref(s), ctypes.byref(t),
+                                         ctypes.byref(grid), ctypes.byref(g)))
+        return {"variant": v.value, "schedule": s.value, "tiles": t.value, "grid": grid.value, "graph": bool(g.value)}
 
     def close(self):
         if self.handle:
@@ -352,8 +361,12 @@ class Server:
     """A continuous-batching request loop (mm_serve_*)."""
 
     def __init__(self, budget_bytes: int, slots: int = 4, max_batch: int = 64, queue_capacity: int = 1 << 16,
-                 device: int = 0, dry_run_tflops: float = 0.0, dry_run_fail_id: int = 0):
-        cfg = ServeConfig(budget_bytes, slots, max_batch, queue_capacity, device, dry_run_tflops, dry_run_fail_id)
+                 device: int = 0, dry_run_tflops: float = 0.0, dry_run_fail_id: int = 0, variants=None,
+                 variants_large=None, large_mn: int = 0):
+        v = (ctypes.c_int32 * 4)(*(variants if variants is not None else (-1, -1, -1, -1)))
+        vl = (ctypes.c_int32 * 4)(*(variants_large if variants_large is not None else (-1, -1, -1, -1)))
+        cfg = ServeConfig(budget_bytes, slots, max_batch, queue_capacity, device, dry_run_tflops, dry_run_fail_id,
+                          v, vl, large_mn)
         self.handle = ctypes.c_void_p(None)
         check(lib().mm_serve_create(ctypes.byref(cfg), ctypes.byref(self.handle)))
 

@@ -185,7 +185,8 @@ mm_status mm_split_bf16(int64_t rows, int64_t cols, const float *X, int64_t ldx,
         return fail(MM_E_INVAL, "planes overlap X");
     mm_status s = check_arch();
     if (s != MM_OK) return s;
-    MM_HIP(launch_split(rows, cols, X, ldx, nplanes, transpose, planes, plane_stride, (hipStream_t)stream));
+    MM_HIP(launch_split(rows, cols, X, ldx, nplanes, transpose, planes, plane_stride, transpose ? rows : cols,
+                        (hipStream_t)stream));
     return MM_OK;
     MM_GUARD_END
 }
@@ -215,9 +216,10 @@ static mm_status run_split(int variant, int64_t M, int64_t N, int64_t K, const f
     const int np = nprod == 3 ? 2 : 3;
     uint16_t *Ap = (uint16_t *)ws;
     uint16_t *Bt = (uint16_t *)((char *)ws + split_b_offset_bytes(M, K, nprod));
-    hipError_t e = launch_split(M, K, A, lda, np, 0, Ap, M * K, st);
-    if (e == hipSuccess) e = launch_split(K, N, B, ldb, np, 1, Bt, N * K, st);
-    if (e == hipSuccess) e = launch_gemm_split(variant, nprod, M, N, K, Ap, Bt, C, ldc, c_is_f64, st);
+    const int64_t Kp = split_padded_k(K);
+    hipError_t e = launch_split(M, K, A, lda, np, 0, Ap, M * Kp, Kp, st);
+    if (e == hipSuccess) e = launch_split(K, N, B, ldb, np, 1, Bt, N * Kp, Kp, st);
+    if (e == hipSuccess) e = launch_gemm_split(variant, nprod, M, N, Kp, Ap, Bt, C, ldc, c_is_f64, st);
     if (owned) {
         hipError_t e2 = hipFreeAsync(ws, st);
         if (e == hipSuccess) e = e2;

@@ -67,7 +67,7 @@ __global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 ? 2 : 1)) void grouped_gem
 }
 
 template <typename ST>
-__global__ __launch_bounds__(ST::NT) void grouped_split_gemm_kernel(const GroupedDesc *__restrict__ descs, int count,
+__global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void grouped_split_gemm_kernel(const GroupedDesc *__restrict__ descs, int count,
                                                                     int64_t total_tiles, int *counter) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
     __shared__ int64_t slot;
@@ -102,12 +102,13 @@ __global__ __launch_bounds__(256) void grouped_split_kernel(const SplitJob *__re
         }
         __syncthreads();
         for (int i = ty; i < 64; i += 4) {
-            // transposed: output row c0+i walks r; plain: output row r0+i walks c
+            // transposed: output row c0+i walks r; plain: output row r0+i walks c.
+            // Output rows hold j.ldp elements; the tail past the data is zero.
             const int64_t r = j.transpose ? r0 + tx : r0 + i;
             const int64_t c = j.transpose ? c0 + i : c0 + tx;
-            if (r < j.rows && c < j.cols) {
+            if (j.transpose ? (r < j.ldp && c < j.cols) : (r < j.rows && c < j.ldp)) {
                 float v = j.transpose ? tile[tx][i] : tile[i][tx];
-                const int64_t o = j.transpose ? c * j.rows + r : r * j.cols + c;
+                const int64_t o = j.transpose ? c * j.ldp + r : r * j.ldp + c;
                 for (int p = 0; p < j.nplanes; ++p) {
                     const uint16_t h = split_bf16_bits(v);
                     j.planes[p * j.pstride + o] = h;
@@ -138,10 +139,10 @@ static KernelInfo kernel_for(mm_method method, int variant) {
     case id: k.fn = (KernelPtr)&grouped_gemm_kernel<TileGemm<double, bm_, bn_, bk, wm, wn>, double>; k.nt = TileGemm<double, bm_, bn_, bk, wm, wn>::NT; k.bm = bm_; k.bn = bn_; break;
 #define MM_GK_F32(id, bm_, bn_, bk, wm, wn) \
     case id: k.fn = (KernelPtr)&grouped_gemm_kernel<TileGemm<float, bm_, bn_, bk, wm, wn>, float>; k.nt = TileGemm<float, bm_, bn_, bk, wm, wn>::NT; k.bm = bm_; k.bn = bn_; break;
-#define MM_GK_S3(id, bm_, bn_, bk, wm, wn) \
-    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTile<3, bm_, bn_, bk, wm, wn>>; k.nt = SplitTile<3, bm_, bn_, bk, wm, wn>::NT; k.bm = bm_; k.bn = bn_; break;
-#define MM_GK_S6(id, bm_, bn_, bk, wm, wn) \
-    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTile<6, bm_, bn_, bk, wm, wn>>; k.nt = SplitTile<6, bm_, bn_, bk, wm, wn>::NT; k.bm = bm_; k.bn = bn_; break;
+#define MM_GK_S3(id, bm_, bn_, bk, wm, wn, st) \
+    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTile<3, bm_, bn_, bk, wm, wn, st>>; k.nt = SplitTile<3, bm_, bn_, bk, wm, wn, st>::NT; k.bm = bm_; k.bn = bn_; break;
+#define MM_GK_S6(id, bm_, bn_, bk, wm, wn, st) \
+    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTile<6, bm_, bn_, bk, wm, wn, st>>; k.nt = SplitTile<6, bm_, bn_, bk, wm, wn, st>::NT; k.bm = bm_; k.bn = bn_; break;
     switch (method) {
         case MM_F64: switch (variant) { MM_F64_VARIANTS(MM_GK_F64) default: break; } break;
         case MM_F32: switch (variant) { MM_F32_VARIANTS(MM_GK_F32) default: break; } break;
@@ -207,21 +208,23 @@ void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_met
         d.tile_begin = L->total_tiles;
         L->total_tiles += cdiv(p.M, bm) * d.tiles_n;
         if (split) {
-            const size_t abytes = align256((size_t)np * p.M * p.K * 2);
-            const size_t bbytes = align256((size_t)np * p.N * p.K * 2);
+            const int64_t Kp = split_padded_k(p.K);
+            const size_t abytes = align256((size_t)np * p.M * Kp * 2);
+            const size_t bbytes = align256((size_t)np * p.N * Kp * 2);
             uint16_t *ap = ws ? (uint16_t *)(ws + off) : nullptr;
             uint16_t *bp = ws ? (uint16_t *)(ws + off + abytes) : nullptr;
             off += abytes + bbytes;
             d.A = ap;
             d.B = bp;
-            d.lda = p.K;
-            d.ldb = p.K;
+            d.K = Kp;     // the planes carry K rounded up to 8, zero-filled
+            d.lda = Kp;
+            d.ldb = Kp;
             if (p.K > 0) {
-                SplitJob ja{(const float *)p.A, p.lda, p.M, p.K, ap, p.M * p.K, L->split_tiles,
+                SplitJob ja{(const float *)p.A, p.lda, p.M, p.K, ap, p.M * Kp, Kp, L->split_tiles,
                             (int32_t)cdiv(p.K, 64), np, 0, 0};
                 L->split_tiles += cdiv(p.M, 64) * ja.tiles_c;
                 L->jobs.push_back(ja);
-                SplitJob jb{(const float *)p.B, p.ldb, p.K, p.N, bp, p.N * p.K, L->split_tiles,
+                SplitJob jb{(const float *)p.B, p.ldb, p.K, p.N, bp, p.N * Kp, Kp, L->split_tiles,
                             (int32_t)cdiv(p.N, 64), np, 1, 0};
                 L->split_tiles += cdiv(p.K, 64) * jb.tiles_c;
                 L->jobs.push_back(jb);
@@ -469,6 +472,15 @@ mm_status mm_gemm_grouped(const mm_problem *probs, int32_t count, mm_method meth
     }
 }
 
+mm_status mm_grouped_plan_launch(mm_grouped_plan *plan, void *stream) {
+    try {
+        if (!plan) return fail(MM_E_INVAL, "plan is NULL");
+        return run_plan(plan, nullptr, (hipStream_t)stream, false);
+    } catch (...) {
+        return fail(MM_E_DEVICE, "internal error");
+    }
+}
+
 mm_status mm_grouped_plan_destroy(mm_grouped_plan *plan) {
     try {
         destroy_plan(plan);
@@ -478,11 +490,17 @@ mm_status mm_grouped_plan_destroy(mm_grouped_plan *plan) {
     }
 }
 
-mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out, int64_t *tiles_out,
-                               int32_t *uses_graph_out) {
+mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out, int32_t *schedule_out,
+                               int64_t *tiles_out, int32_t *grid_out, int32_t *uses_graph_out) {
     if (!plan) return fail(MM_E_INVAL, "plan is NULL");
     if (variant_out) *variant_out = plan->variant;
+    if (schedule_out) *schedule_out = plan->schedule;
     if (tiles_out) *tiles_out = plan->layout.total_tiles;
+    if (grid_out) {
+        const KernelInfo k = kernel_for(plan->method, plan->variant);
+        int64_t g = persistent_grid(plan->method, plan->variant, k.fn, k.nt);
+        *grid_out = (int32_t)(g < plan->layout.total_tiles ? g : plan->layout.total_tiles);
+    }
     if (uses_graph_out) *uses_graph_out = plan->exec != nullptr;
     return MM_OK;
 }

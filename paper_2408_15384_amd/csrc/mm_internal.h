@@ -50,12 +50,16 @@ hipError_t launch_gemm_f64(int variant, int64_t M, int64_t N, int64_t K, const d
 hipError_t launch_gemm_f32(int variant, int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
                            const float *B, int64_t ldb, float *C, int64_t ldc, hipStream_t stream);
 
-// Split pass: FP32 -> nplanes bfloat16 planes (optionally transposed).
+// Split pass: FP32 -> nplanes bfloat16 planes (optionally transposed); output
+// rows hold ldp elements (>= the row length), the tail written as zero.
 hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx, int nplanes, int transpose,
-                        uint16_t *planes, int64_t plane_stride, hipStream_t stream);
+                        uint16_t *planes, int64_t plane_stride, int64_t ldp, hipStream_t stream);
+// Row length of the planes the split GEMM reads: K rounded up to 8.
+int64_t split_padded_k(int64_t K);
 
 // Split GEMM on planes: A planes M x K row-major (stride M*K), B planes stored
-// transposed N x K (stride N*K); C FP32 or binary64.
+// transposed N x K (stride N*K), K already padded (split_padded_k); C FP32 or
+// binary64.
 hipError_t launch_gemm_split(int variant, int nprod, int64_t M, int64_t N, int64_t K, const uint16_t *Ap,
                              const uint16_t *Bt, void *C, int64_t ldc, int c_is_f64, hipStream_t stream);
 
@@ -90,6 +94,7 @@ struct SplitJob {
     int64_t ldx, rows, cols;
     uint16_t *planes;
     int64_t pstride;
+    int64_t ldp;          // output row length (>= row length; tail zero)
     int64_t tile_begin;
     int32_t tiles_c;
     int32_t nplanes;

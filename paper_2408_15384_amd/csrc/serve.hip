@@ -27,6 +27,7 @@
 #include <cstring>
 #include <deque>
 #include <mutex>
+#include <string>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -58,14 +59,18 @@ struct Slot {
     uint64_t bytes = 0;
     double flop = 0;
     double dry_done_at = 0;
-    // per method group: device descriptors / split jobs and pinned staging
+    // per (method, class) group: device descriptors / split jobs, pinned
+    // staging and a work counter
+    int *d_counters = nullptr;
+    char *ws = nullptr;       // split workspace, grown when a batch needs more
+    size_t ws_cap = 0;
     GroupedDesc *d_descs = nullptr;
     SplitJob *d_jobs = nullptr;
     GroupedDesc *h_descs = nullptr;
     SplitJob *h_jobs = nullptr;
 };
 
-constexpr int kGroups = 4;  // one grouped launch per method
+constexpr int kGroups = 8;  // one grouped launch per (method, size class)
 
 uint64_t elem_bytes(mm_method m) { return m == MM_F64 ? 8 : 4; }
 
@@ -77,8 +82,11 @@ uint64_t request_bytes(const mm_problem &p, mm_method m) {
     return b;
 }
 
-// Fixed variant per method for served requests (mid-size bucket).
-int serve_variant(mm_method m) { return select_variant(m, 1024, 1024, 1024); }
+// Default variant per method and size class: the single-product rule for a
+// 2048^3 (large) or 256^3 (small) product.
+int default_serve_variant(mm_method m, bool large) {
+    return large ? select_variant(m, 2048, 2048, 2048) : select_variant(m, 256, 256, 256);
+}
 
 }  // namespace
 }  // namespace mm
@@ -97,6 +105,8 @@ struct mm_server {
     uint64_t in_flight_bytes = 0;
     uint64_t peak_bytes = 0;
     std::vector<mm::Slot> slots;
+    int variant[8];  // index: method + 4 * large
+    int64_t large_mn = 0;
     std::thread thread;
     bool stopping = false;
     // statistics
@@ -149,36 +159,57 @@ static mm_status launch(mm_server *s, Slot &slot, const std::vector<uint64_t> &i
         return MM_OK;
     }
     const int cap = s->cfg.max_batch;
+    // group the batch by (method, size class) and size the split workspace
+    std::vector<mm_problem> probs[kGroups];
+    std::vector<int> order[kGroups];
+    Layout L[kGroups];
+    size_t ws_need = 0;
     for (int g = 0; g < kGroups; ++g) {
-        const mm_method m = (mm_method)g;
-        std::vector<mm_problem> probs;
-        for (uint64_t id : ids)
-            if (s->reqs[id].method == m) probs.push_back(s->reqs[id].p);
-        if (probs.empty()) continue;
-        const int variant = serve_variant(m);
-        const int bm = grouped_tile_bm(m, variant), bn = grouped_tile_bn(m, variant);
-        std::vector<int> order = schedule_order(probs.data(), (int)probs.size(), 1);
-        Layout L;
-        build_layout(probs.data(), order, m, bm, bn, nullptr, &L);
-        if (L.descs.empty()) continue;
-        char *ws = nullptr;
-        if (L.ws_bytes) {
-            MM_HIP(hipMallocAsync((void **)&ws, L.ws_bytes, slot.stream));
-            build_layout(probs.data(), order, m, bm, bn, ws, &L);
+        const mm_method m = (mm_method)(g % 4);
+        const bool large = g >= 4;
+        for (uint64_t id : ids) {
+            const Request &r = s->reqs[id];
+            if (r.method == m && ((r.p.M * r.p.N >= s->large_mn) == large)) probs[g].push_back(r.p);
+        }
+        if (probs[g].empty()) continue;
+        const int variant = s->variant[g];
+        order[g] = schedule_order(probs[g].data(), (int)probs[g].size(), 2);
+        build_layout(probs[g].data(), order[g], m, grouped_tile_bm(m, variant), grouped_tile_bn(m, variant), nullptr,
+                     &L[g]);
+        ws_need += (L[g].ws_bytes + 255) & ~(size_t)255;
+    }
+    if (ws_need > slot.ws_cap) {
+        // the slot is idle (its previous launch has retired), so its old buffer is free
+        if (slot.ws) MM_HIP(hipFree(slot.ws));
+        slot.ws = nullptr;
+        slot.ws_cap = 0;
+        const size_t want = ws_need + ws_need / 2;
+        MM_HIP(hipMalloc((void **)&slot.ws, want));
+        slot.ws_cap = want;
+    }
+    size_t ws_off = 0;
+    for (int g = 0; g < kGroups; ++g) {
+        if (probs[g].empty()) continue;
+        const mm_method m = (mm_method)(g % 4);
+        const int variant = s->variant[g];
+        if (L[g].descs.empty()) continue;
+        if (L[g].ws_bytes) {
+            build_layout(probs[g].data(), order[g], m, grouped_tile_bm(m, variant), grouped_tile_bn(m, variant),
+                         slot.ws + ws_off, &L[g]);
+            ws_off += (L[g].ws_bytes + 255) & ~(size_t)255;
         }
         GroupedDesc *hd = slot.h_descs + (size_t)g * cap;
         SplitJob *hj = slot.h_jobs + (size_t)g * 2 * cap;
-        std::memcpy(hd, L.descs.data(), L.descs.size() * sizeof(GroupedDesc));
+        std::memcpy(hd, L[g].descs.data(), L[g].descs.size() * sizeof(GroupedDesc));
         GroupedDesc *dd = slot.d_descs + (size_t)g * cap;
         SplitJob *dj = slot.d_jobs + (size_t)g * 2 * cap;
-        MM_HIP(hipMemcpyAsync(dd, hd, L.descs.size() * sizeof(GroupedDesc), hipMemcpyHostToDevice, slot.stream));
-        if (!L.jobs.empty()) {
-            std::memcpy(hj, L.jobs.data(), L.jobs.size() * sizeof(SplitJob));
-            MM_HIP(hipMemcpyAsync(dj, hj, L.jobs.size() * sizeof(SplitJob), hipMemcpyHostToDevice, slot.stream));
+        MM_HIP(hipMemcpyAsync(dd, hd, L[g].descs.size() * sizeof(GroupedDesc), hipMemcpyHostToDevice, slot.stream));
+        if (!L[g].jobs.empty()) {
+            std::memcpy(hj, L[g].jobs.data(), L[g].jobs.size() * sizeof(SplitJob));
+            MM_HIP(hipMemcpyAsync(dj, hj, L[g].jobs.size() * sizeof(SplitJob), hipMemcpyHostToDevice, slot.stream));
         }
-        MM_HIP(grouped_enqueue(m, variant, dd, (int)L.descs.size(), L.total_tiles, dj, (int)L.jobs.size(),
-                               L.split_tiles, nullptr, slot.stream));
-        if (ws) MM_HIP(hipFreeAsync(ws, slot.stream));
+        MM_HIP(grouped_enqueue(m, variant, dd, (int)L[g].descs.size(), L[g].total_tiles, dj, (int)L[g].jobs.size(),
+                               L[g].split_tiles, slot.d_counters + g, slot.stream));
     }
     MM_HIP(hipEventRecord(slot.done, slot.stream));
     return MM_OK;
@@ -235,6 +266,8 @@ static void release(mm_server *s) {
     for (Slot &slot : s->slots) {
         if (slot.done) (void)hipEventDestroy(slot.done);
         if (slot.stream) (void)hipStreamDestroy(slot.stream);
+        if (slot.d_counters) (void)hipFree(slot.d_counters);
+        if (slot.ws) (void)hipFree(slot.ws);
         if (slot.d_descs) (void)hipFree(slot.d_descs);
         if (slot.d_jobs) (void)hipFree(slot.d_jobs);
         if (slot.h_descs) (void)hipHostFree(slot.h_descs);
@@ -256,8 +289,19 @@ mm_status mm_serve_create(const mm_serve_config *cfg, mm_server **out) {
         if (cfg->max_batch < 1 || cfg->max_batch > 4096) return fail(MM_E_INVAL, "max_batch must be 1..4096");
         if (cfg->queue_capacity < 1) return fail(MM_E_INVAL, "queue_capacity must be positive");
         if (cfg->budget_bytes == 0) return fail(MM_E_INVAL, "budget_bytes must be positive");
+        for (int m = 0; m < 4; ++m)
+            if (cfg->variants[m] < -1 || cfg->variants[m] >= mm_variant_count((mm_method)m) ||
+                cfg->variants_large[m] < -1 || cfg->variants_large[m] >= mm_variant_count((mm_method)m))
+                return fail(MM_E_INVAL, "no such variant for method " + std::to_string(m));
+        if (cfg->large_mn < 0) return fail(MM_E_INVAL, "large_mn must be >= 0");
         mm_server *s = new mm_server();
         s->cfg = *cfg;
+        s->large_mn = cfg->large_mn > 0 ? cfg->large_mn : (int64_t)1024 * 1024;
+        for (int m = 0; m < 4; ++m) {
+            s->variant[m] = cfg->variants[m] >= 0 ? cfg->variants[m] : default_serve_variant((mm_method)m, false);
+            s->variant[m + 4] =
+                cfg->variants_large[m] >= 0 ? cfg->variants_large[m] : default_serve_variant((mm_method)m, true);
+        }
         s->dry_tflops = cfg->dry_run_tflops;
         s->dry_fail_id = cfg->dry_run_fail_id;
         s->t0 = Clock::now();
@@ -269,6 +313,7 @@ mm_status mm_serve_create(const mm_serve_config *cfg, mm_server **out) {
             for (Slot &slot : s->slots) {
                 if (e == hipSuccess) e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
                 if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
+                if (e == hipSuccess) e = hipMalloc(&slot.d_counters, kGroups * sizeof(int));
                 if (e == hipSuccess) e = hipMalloc(&slot.d_descs, kGroups * cap * sizeof(GroupedDesc));
                 if (e == hipSuccess) e = hipMalloc(&slot.d_jobs, kGroups * 2 * cap * sizeof(SplitJob));
                 if (e == hipSuccess) e = hipHostMalloc((void **)&slot.h_descs, kGroups * cap * sizeof(GroupedDesc), 0);

@@ -14,10 +14,11 @@ namespace mm {
 
 
 // ------------------------------------------------------------------ split pass
-// Row-major planes: each thread splits 4 consecutive elements of one row.
+// Row-major planes with rows of ldp >= cols elements (columns cols..ldp-1
+// written as zero): each thread splits 4 consecutive elements of one row.
 __global__ void split_rows_kernel(const float *__restrict__ X, int64_t ldx, int64_t rows, int64_t cols, int nplanes,
-                                  uint16_t *__restrict__ planes, int64_t plane_stride) {
-    const int64_t quads_per_row = (cols + 3) / 4;
+                                  uint16_t *__restrict__ planes, int64_t plane_stride, int64_t ldp) {
+    const int64_t quads_per_row = (ldp + 3) / 4;
     const int64_t total = rows * quads_per_row;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = t / quads_per_row;
@@ -27,22 +28,23 @@ __global__ void split_rows_kernel(const float *__restrict__ X, int64_t ldx, int6
 #pragma unroll
         for (int e = 0; e < 4; ++e) v[e] = (c0 + e < cols) ? src[e] : 0.f;
         for (int p = 0; p < nplanes; ++p) {
-            uint16_t *dst = planes + p * plane_stride + r * cols + c0;
+            uint16_t *dst = planes + p * plane_stride + r * ldp + c0;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const uint16_t h = split_bf16_bits(v[e]);
-                if (c0 + e < cols) dst[e] = h;
+                if (c0 + e < ldp) dst[e] = h;
                 v[e] = v[e] - split_bf16_value(h);
             }
         }
     }
 }
 
-// Transposed planes: 64 x 64 tiles through LDS so both the FP32 reads (along
-// a row of X) and the bfloat16 writes (along a row of X^T) are coalesced.
+// Transposed planes (rows of X^T hold ldp >= rows elements, the tail written
+// as zero): 64 x 64 tiles through LDS so both the FP32 reads (along a row of
+// X) and the bfloat16 writes (along a row of X^T) are coalesced.
 __global__ __launch_bounds__(256) void split_transpose_kernel(const float *__restrict__ X, int64_t ldx, int64_t rows,
                                                               int64_t cols, int nplanes, uint16_t *__restrict__ planes,
-                                                              int64_t plane_stride) {
+                                                              int64_t plane_stride, int64_t ldp) {
     __shared__ float tile[64][65];
     const int64_t tiles_c = (cols + 63) / 64;
     const int64_t r0 = (blockIdx.x / tiles_c) * 64;
@@ -56,42 +58,48 @@ __global__ __launch_bounds__(256) void split_transpose_kernel(const float *__res
     // output element (c, r) of X^T: thread tx walks r
     for (int j = ty; j < 64; j += 4) {
         const int64_t c = c0 + j, r = r0 + tx;
-        if (c >= cols || r >= rows) continue;
+        if (c >= cols || r >= ldp) continue;
         float v = tile[tx][j];
         for (int p = 0; p < nplanes; ++p) {
             const uint16_t h = split_bf16_bits(v);
-            planes[p * plane_stride + c * rows + r] = h;
+            planes[p * plane_stride + c * ldp + r] = h;
             v = v - split_bf16_value(h);
         }
     }
 }
 
 hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx, int nplanes, int transpose,
-                        uint16_t *planes, int64_t plane_stride, hipStream_t stream) {
+                        uint16_t *planes, int64_t plane_stride, int64_t ldp, hipStream_t stream) {
     if (rows <= 0 || cols <= 0) return hipSuccess;
     if (transpose) {
+        // 64-row tiles cover ldp: ldp <= round_up(rows, 64)
         const int64_t blocks = ((rows + 63) / 64) * ((cols + 63) / 64);
-        if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+        if (blocks > 0x7fffffffLL || ldp < rows || ldp > (rows + 63) / 64 * 64) return hipErrorInvalidConfiguration;
         hipLaunchKernelGGL(split_transpose_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, X, ldx, rows, cols,
-                           nplanes, planes, plane_stride);
+                           nplanes, planes, plane_stride, ldp);
     } else {
-        int64_t blocks = (rows * ((cols + 3) / 4) + 255) / 256;
+        if (ldp < cols) return hipErrorInvalidConfiguration;
+        int64_t blocks = (rows * ((ldp + 3) / 4) + 255) / 256;
         if (blocks > 1 << 20) blocks = 1 << 20;
         hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, X, ldx, rows, cols,
-                           nplanes, planes, plane_stride);
+                           nplanes, planes, plane_stride, ldp);
     }
     return hipGetLastError();
 }
 
+int64_t split_padded_k(int64_t K) { return (K + 7) / 8 * 8; }
+
+// Planes of the product use rows of split_padded_k(K) elements (zero tail),
+// so every 8-element fragment is one aligned 16-byte access.
 size_t split_b_offset_bytes(int64_t M, int64_t K, int nprod) {
     const int np = nprod == 3 ? 2 : 3;
     // B planes start 256-byte aligned behind the A planes
-    return ((size_t)np * M * K * 2 + 255) & ~(size_t)255;
+    return ((size_t)np * M * split_padded_k(K) * 2 + 255) & ~(size_t)255;
 }
 
 size_t split_workspace_bytes(int64_t M, int64_t N, int64_t K, int nprod) {
     const int np = nprod == 3 ? 2 : 3;
-    return split_b_offset_bytes(M, K, nprod) + (size_t)np * N * K * 2;
+    return split_b_offset_bytes(M, K, nprod) + (size_t)np * N * split_padded_k(K) * 2;
 }
 
 __device__ void tile_order_split(int64_t bid, int64_t tiles_m, int64_t tiles_n, int64_t *tm, int64_t *tn) {
@@ -109,7 +117,7 @@ __device__ void tile_order_split(int64_t bid, int64_t tiles_m, int64_t tiles_n, 
 }
 
 template <typename ST>
-__global__ __launch_bounds__(ST::NT) void split_gemm_kernel(const uint16_t *__restrict__ Ap, int64_t pa_stride,
+__global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void split_gemm_kernel(const uint16_t *__restrict__ Ap, int64_t pa_stride,
                                                             const uint16_t *__restrict__ Bt, int64_t pb_stride,
                                                             void *C, int64_t ldc, int c_is_f64, int64_t M, int64_t N,
                                                             int64_t K, int64_t tiles_m, int64_t tiles_n, int vec_ok) {
@@ -133,18 +141,19 @@ static hipError_t launch_split_tile(int64_t M, int64_t N, int64_t K, const uint1
     return hipGetLastError();
 }
 
-#define MM_S_COUNT(id, bm, bn, bk, wm, wn) +1
-#define MM_S_CFG(id, bm, bn, bk, wm, wn) case id: return TileCfg{bm, bn, bk};
+#define MM_S_COUNT(id, bm, bn, bk, wm, wn, st) +1
+#define MM_S_CFG(id, bm, bn, bk, wm, wn, st) case id: return TileCfg{bm, bn, bk};
 int split_variant_count() { return 0 MM_SPLIT_VARIANTS(MM_S_COUNT); }
 TileCfg split_variant(int v) {
     switch (v) { MM_SPLIT_VARIANTS(MM_S_CFG) default: return TileCfg{0, 0, 0}; }
 }
 
-#define MM_S_LAUNCH(id, bm, bn, bk, wm, wn)                                                                        \
+#define MM_S_LAUNCH(id, bm, bn, bk, wm, wn, st)                                                                   \
     case id:                                                                                                       \
-        return nprod == 3                                                                                          \
-                   ? launch_split_tile<SplitTile<3, bm, bn, bk, wm, wn>>(M, N, K, Ap, Bt, C, ldc, c_is_f64, stream) \
-                   : launch_split_tile<SplitTile<6, bm, bn, bk, wm, wn>>(M, N, K, Ap, Bt, C, ldc, c_is_f64, stream);
+        return nprod == 3 ? launch_split_tile<SplitTile<3, bm, bn, bk, wm, wn, st>>(M, N, K, Ap, Bt, C, ldc, c_is_f64, \
+                                                                                     stream)                       \
+                          : launch_split_tile<SplitTile<6, bm, bn, bk, wm, wn, st>>(M, N, K, Ap, Bt, C, ldc, c_is_f64, \
+                                                                                     stream);
 
 hipError_t launch_gemm_split(int variant, int nprod, int64_t M, int64_t N, int64_t K, const uint16_t *Ap,
                              const uint16_t *Bt, void *C, int64_t ldc, int c_is_f64, hipStream_t stream) {

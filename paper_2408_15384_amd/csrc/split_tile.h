@@ -40,21 +40,29 @@ template <> struct SplitTerms<6> {
     static constexpr int pb[6] = {0, 1, 0, 2, 1, 0};
 };
 
-template <int NPROD, int BM_, int BN_, int BK_, int WM_, int WN_>
+template <int NPROD, int BM_, int BN_, int BK_, int WM_, int WN_, int STAGES_ = 1>
 struct SplitTile {
     using Terms = SplitTerms<NPROD>;
     static constexpr int NP = Terms::NP;
-    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, STAGES = STAGES_;
     static constexpr int NWN = BN / WN;
     static constexpr int NWAVES = (BM / WM) * (BN / WN);
     static constexpr int NT = NWAVES * 64;
     static constexpr int FM = WM / 16, FN = WN / 16;
     static constexpr int KSTEPS = BK / 32;
-    static constexpr int LD = BK + 8;                 // bf16 elements per LDS row (16-byte pad)
+    // LDS rows hold BK bf16 with no padding; the 16-byte chunks of a row are
+    // permuted (chunk ^ swz(row)) so that the 16 lanes of a fragment read (16
+    // rows, one chunk) and of a store (whole rows) touch 16 distinct 16-byte
+    // bank groups.
+    static constexpr int LD = BK;
     static constexpr int A_PLANE = BM * LD, B_PLANE = BN * LD;
     static constexpr int STAGE = NP * (A_PLANE + B_PLANE);
     static constexpr int LDS_ELEMS = 2 * STAGE;
     static constexpr int VROW = BK / 8;               // 16-byte vectors per row
+    static constexpr int ROWS_PER_256B = 256 / (VROW * 16) > 0 ? 256 / (VROW * 16) : 1;
+    static __device__ __forceinline__ int swz(int row, int chunk) {
+        return chunk ^ ((row / ROWS_PER_256B) & (VROW - 1));
+    }
     static constexpr int A_VECS = NP * BM * VROW / NT;
     static constexpr int B_VECS = NP * BN * VROW / NT;
     static_assert(BK % 32 == 0, "BK multiple of 32");
@@ -93,12 +101,12 @@ struct SplitTile {
             const int rem = v % (rows_tile * VROW);
             const int r = rem / VROW;
             const int c = (rem % VROW) * 8;
-            *reinterpret_cast<u16x8 *>(lds + p * plane_elems + r * LD + c) = regs[i];
+            *reinterpret_cast<u16x8 *>(lds + p * plane_elems + r * LD + swz(r, c / 8) * 8) = regs[i];
         }
     }
 
     static __device__ __forceinline__ bf16x8 frag(const uint16_t *lds, int row, int kofs) {
-        return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(lds + row * LD + kofs));
+        return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(lds + row * LD + swz(row, kofs / 8) * 8));
     }
 
     static __device__ __forceinline__ void compute(const uint16_t *As, const uint16_t *Bs, f32x4 (&lead)[FM][FN],
@@ -147,27 +155,70 @@ struct SplitTile {
                 lead[fm][fn] = f32x4{0, 0, 0, 0};
                 corr[fm][fn] = f32x4{0, 0, 0, 0};
             }
-        u16x8 ra[A_VECS], rb[B_VECS];
-        const int64_t nkt = (K + BK - 1) / BK;
-        load(ra, A_VECS, Ap, pa_stride, m0, M, K, 0, BM, vec_ok);
-        load(rb, B_VECS, Bt, pb_stride, n0, N, K, 0, BN, vec_ok);
-        store(smem, A_PLANE, ra, A_VECS, BM);
-        store(smem + NP * A_PLANE, B_PLANE, rb, B_VECS, BN);
-        __syncthreads();
-        for (int64_t kt = 0; kt < nkt; ++kt) {
-            const bool more = kt + 1 < nkt;
-            if (more) {
-                load(ra, A_VECS, Ap, pa_stride, m0, M, K, (kt + 1) * BK, BM, vec_ok);
-                load(rb, B_VECS, Bt, pb_stride, n0, N, K, (kt + 1) * BK, BN, vec_ok);
-            }
-            const uint16_t *cur = smem + (kt & 1) * STAGE;
-            compute(cur, cur + NP * A_PLANE, lead, corr);
-            if (more) {
-                uint16_t *nxt = smem + ((kt + 1) & 1) * STAGE;
-                store(nxt, A_PLANE, ra, A_VECS, BM);
-                store(nxt + NP * A_PLANE, B_PLANE, rb, B_VECS, BN);
-            }
+        if (STAGES == 1) {
+            // One register stage: slice kt+1 is loaded while slice kt is multiplied.
+            u16x8 ra[A_VECS], rb[B_VECS];
+            const int64_t nkt = (K + BK - 1) / BK;
+            load(ra, A_VECS, Ap, pa_stride, m0, M, K, 0, BM, vec_ok);
+            load(rb, B_VECS, Bt, pb_stride, n0, N, K, 0, BN, vec_ok);
+            store(smem, A_PLANE, ra, A_VECS, BM);
+            store(smem + NP * A_PLANE, B_PLANE, rb, B_VECS, BN);
             __syncthreads();
+            for (int64_t kt = 0; kt < nkt; ++kt) {
+                const bool more = kt + 1 < nkt;
+                if (more) {
+                    load(ra, A_VECS, Ap, pa_stride, m0, M, K, (kt + 1) * BK, BM, vec_ok);
+                    load(rb, B_VECS, Bt, pb_stride, n0, N, K, (kt + 1) * BK, BN, vec_ok);
+                }
+                const uint16_t *cur = smem + (kt & 1) * STAGE;
+                compute(cur, cur + NP * A_PLANE, lead, corr);
+                if (more) {
+                    uint16_t *nxt = smem + ((kt + 1) & 1) * STAGE;
+                    store(nxt, A_PLANE, ra, A_VECS, BM);
+                    store(nxt + NP * A_PLANE, B_PLANE, rb, B_VECS, BN);
+                }
+                __syncthreads();
+            }
+        } else {
+            // Global loads run two K steps ahead of the MFMAs (two register stages,
+            // double-buffered LDS): slice kt+2 is requested while slice kt is
+            // multiplied and slice kt+1 waits in registers for its LDS buffer.
+            u16x8 ra0[A_VECS], rb0[B_VECS], ra1[A_VECS], rb1[B_VECS];
+            const int64_t nkt = (K + BK - 1) / BK;
+            load(ra0, A_VECS, Ap, pa_stride, m0, M, K, 0, BM, vec_ok);
+            load(rb0, B_VECS, Bt, pb_stride, n0, N, K, 0, BN, vec_ok);
+            if (nkt > 1) {
+                load(ra1, A_VECS, Ap, pa_stride, m0, M, K, BK, BM, vec_ok);
+                load(rb1, B_VECS, Bt, pb_stride, n0, N, K, BK, BN, vec_ok);
+            }
+            store(smem, A_PLANE, ra0, A_VECS, BM);
+            store(smem + NP * A_PLANE, B_PLANE, rb0, B_VECS, BN);
+            __syncthreads();
+            for (int64_t kt = 0; kt < nkt; kt += 2) {
+                // even step kt: register set 1 holds slice kt+1; refill set 0 with kt+2
+                if (kt + 2 < nkt) {
+                    load(ra0, A_VECS, Ap, pa_stride, m0, M, K, (kt + 2) * BK, BM, vec_ok);
+                    load(rb0, B_VECS, Bt, pb_stride, n0, N, K, (kt + 2) * BK, BN, vec_ok);
+                }
+                compute(smem, smem + NP * A_PLANE, lead, corr);
+                if (kt + 1 < nkt) {
+                    store(smem + STAGE, A_PLANE, ra1, A_VECS, BM);
+                    store(smem + STAGE + NP * A_PLANE, B_PLANE, rb1, B_VECS, BN);
+                }
+                __syncthreads();
+                if (kt + 1 >= nkt) break;
+                // odd step kt+1: set 0 holds slice kt+2; refill set 1 with kt+3
+                if (kt + 3 < nkt) {
+                    load(ra1, A_VECS, Ap, pa_stride, m0, M, K, (kt + 3) * BK, BM, vec_ok);
+                    load(rb1, B_VECS, Bt, pb_stride, n0, N, K, (kt + 3) * BK, BN, vec_ok);
+                }
+                compute(smem + STAGE, smem + STAGE + NP * A_PLANE, lead, corr);
+                if (kt + 2 < nkt) {
+                    store(smem, A_PLANE, ra0, A_VECS, BM);
+                    store(smem + NP * A_PLANE, B_PLANE, rb0, B_VECS, BN);
+                }
+                __syncthreads();
+            }
         }
         // binary64 recombination of the two accumulator sets
         const int lane = threadIdx.x & 63;

@@ -17,7 +17,11 @@
     X(2, 256, 128, 16, 64, 64)        \
     X(3, 128, 128, 32, 64, 64)
 
+// Split variants carry a seventh field, S: register stages of global prefetch.
 #define MM_SPLIT_VARIANTS(X)          \
-    X(0, 128, 128, 32, 64, 64)        \
-    X(1, 64, 64, 32, 32, 32)          \
-    X(2, 128, 64, 32, 64, 32)
+    X(0, 128, 128, 32, 64, 64, 1)     \
+    X(1, 64, 64, 32, 32, 32, 1)       \
+    X(2, 128, 64, 32, 64, 32, 1)      \
+    X(3, 128, 128, 32, 64, 32, 1)     \
+    X(4, 128, 128, 32, 64, 32, 2)     \
+    X(5, 64, 64, 32, 32, 32, 2)

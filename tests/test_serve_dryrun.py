@@ -62,7 +62,10 @@ def test_oversize_request_and_full_queue():
             except api.MMError as err:
                 assert err.status == api.MM_E_BUSY
                 results.append(None)
-        assert results[3] is None and results[4] is None   # first admitted or queued, then 2 queued, rest refused
+        # at most one request in the only slot plus queue_capacity waiting; the
+        # scheduler may or may not have taken the first one yet
+        accepted = [r for r in results if r is not None]
+        assert 2 <= len(accepted) <= 3
         for r in results:
             if r is not None:
                 assert srv.wait(r)[0] == api.MM_OK
