@@ -60,7 +60,8 @@ int default_variant(mm_method method, int64_t M, int64_t N, int64_t K) {
             return 1;
         case MM_SPLIT_BF16_3:
         case MM_SPLIT_BF16_6:
-            if (mn >= (int64_t)512 * 512) return 0;
+            // direct-to-LDS 3-stage ring, 8 waves, for mid and large products
+            if (mn >= (int64_t)512 * 512) return 6;
             return 1;
     }
     return 0;

@@ -140,9 +140,9 @@ static KernelInfo kernel_for(mm_method method, int variant) {
 #define MM_GK_F32(id, bm_, bn_, bk, wm, wn) \
     case id: k.fn = (KernelPtr)&grouped_gemm_kernel<TileGemm<float, bm_, bn_, bk, wm, wn>, float>; k.nt = TileGemm<float, bm_, bn_, bk, wm, wn>::NT; k.bm = bm_; k.bn = bn_; break;
 #define MM_GK_S3(id, bm_, bn_, bk, wm, wn, st) \
-    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTile<3, bm_, bn_, bk, wm, wn, st>>; k.nt = SplitTile<3, bm_, bn_, bk, wm, wn, st>::NT; k.bm = bm_; k.bn = bn_; break;
+    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type>; k.nt = SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
 #define MM_GK_S6(id, bm_, bn_, bk, wm, wn, st) \
-    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTile<6, bm_, bn_, bk, wm, wn, st>>; k.nt = SplitTile<6, bm_, bn_, bk, wm, wn, st>::NT; k.bm = bm_; k.bn = bn_; break;
+    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type>; k.nt = SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
     switch (method) {
         case MM_F64: switch (variant) { MM_F64_VARIANTS(MM_GK_F64) default: break; } break;
         case MM_F32: switch (variant) { MM_F32_VARIANTS(MM_GK_F32) default: break; } break;
@@ -216,7 +216,7 @@ void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_met
             off += abytes + bbytes;
             d.A = ap;
             d.B = bp;
-            d.K = Kp;     // the planes carry K rounded up to 8, zero-filled
+            d.K = Kp;     // the planes carry K rounded up to 32, zero-filled
             d.lda = Kp;
             d.ldb = Kp;
             if (p.K > 0) {

@@ -54,7 +54,7 @@ hipError_t launch_gemm_f32(int variant, int64_t M, int64_t N, int64_t K, const f
 // rows hold ldp elements (>= the row length), the tail written as zero.
 hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx, int nplanes, int transpose,
                         uint16_t *planes, int64_t plane_stride, int64_t ldp, hipStream_t stream);
-// Row length of the planes the split GEMM reads: K rounded up to 8.
+// Row length of the planes the split GEMM reads: K rounded up to 32.
 int64_t split_padded_k(int64_t K);
 
 // Split GEMM on planes: A planes M x K row-major (stride M*K), B planes stored

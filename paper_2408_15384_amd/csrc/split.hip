@@ -87,10 +87,11 @@ hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx,
     return hipGetLastError();
 }
 
-int64_t split_padded_k(int64_t K) { return (K + 7) / 8 * 8; }
+int64_t split_padded_k(int64_t K) { return (K + 31) / 32 * 32; }
 
-// Planes of the product use rows of split_padded_k(K) elements (zero tail),
-// so every 8-element fragment is one aligned 16-byte access.
+// Planes of the product use rows of split_padded_k(K) elements (zero tail):
+// every 8-element fragment is one aligned 16-byte access and every 32-wide K
+// step is whole.
 size_t split_b_offset_bytes(int64_t M, int64_t K, int nprod) {
     const int np = nprod == 3 ? 2 : 3;
     // B planes start 256-byte aligned behind the A planes
@@ -150,10 +151,11 @@ TileCfg split_variant(int v) {
 
 #define MM_S_LAUNCH(id, bm, bn, bk, wm, wn, st)                                                                   \
     case id:                                                                                                       \
-        return nprod == 3 ? launch_split_tile<SplitTile<3, bm, bn, bk, wm, wn, st>>(M, N, K, Ap, Bt, C, ldc, c_is_f64, \
-                                                                                     stream)                       \
-                          : launch_split_tile<SplitTile<6, bm, bn, bk, wm, wn, st>>(M, N, K, Ap, Bt, C, ldc, c_is_f64, \
-                                                                                     stream);
+        return nprod == 3                                                                                          \
+                   ? launch_split_tile<SplitTileSel<3, bm, bn, bk, wm, wn, st>::type>(M, N, K, Ap, Bt, C, ldc,       \
+                                                                                       c_is_f64, stream)            \
+                   : launch_split_tile<SplitTileSel<6, bm, bn, bk, wm, wn, st>::type>(M, N, K, Ap, Bt, C, ldc,       \
+                                                                                       c_is_f64, stream);
 
 hipError_t launch_gemm_split(int variant, int nprod, int64_t M, int64_t N, int64_t K, const uint16_t *Ap,
                              const uint16_t *Bt, void *C, int64_t ldc, int c_is_f64, hipStream_t stream) {

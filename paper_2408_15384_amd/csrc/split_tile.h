@@ -242,4 +242,181 @@ struct SplitTile {
     }
 };
 
+
+// ---------------------------------------------------------------------------
+// Direct-to-LDS variant: global_load_lds_dwordx4 moves each 16-byte chunk of
+// the planes straight into LDS (no staging registers), into a ring of STAGES
+// LDS buffers, so the loads of K steps kt+1 .. kt+STAGES-1 are in flight while
+// step kt is multiplied.  One wave-instruction fills 64 consecutive 16-byte
+// LDS slots (lane i -> slot i); each lane fetches whichever global chunk the
+// swizzled layout puts in its slot.  Rows past M (or N) are clamped to the
+// last row: they only feed entries of C that are not stored.  K is a
+// multiple of 32 (the planes are zero-padded), so no K-tail checks remain.
+typedef __attribute__((address_space(1))) void mm_global_void;
+typedef __attribute__((address_space(3))) void mm_lds_void;
+
+template <int NPROD, int BM_, int BN_, int WM_, int WN_, int STAGES_>
+struct SplitTileDirect {
+    using Terms = SplitTerms<NPROD>;
+    static constexpr int NP = Terms::NP;
+    static constexpr int BM = BM_, BN = BN_, BK = 32, WM = WM_, WN = WN_, STAGES = STAGES_;
+    static constexpr int NWN = BN / WN;
+    static constexpr int NWAVES = (BM / WM) * (BN / WN);
+    static constexpr int NT = NWAVES * 64;
+    static constexpr int FM = WM / 16, FN = WN / 16;
+    static constexpr int ROWS = BM + BN;                 // rows of one plane in a stage: A rows, then B rows
+    static constexpr int PLANE_CHUNKS = ROWS * 4;        // 4 chunks of 16 bytes per 32-element row
+    static constexpr int STAGE_CHUNKS = NP * PLANE_CHUNKS;
+    static constexpr int STAGE_ELEMS = STAGE_CHUNKS * 8;
+    static constexpr int LDS_ELEMS = STAGES * STAGE_ELEMS;
+    static constexpr int LOADS = STAGE_CHUNKS / NT;      // load instructions per thread per stage
+    static_assert(STAGE_CHUNKS % NT == 0, "stage must split evenly over the threads");
+    static_assert(STAGES >= 2 && STAGES <= 4, "stages");
+
+    static __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 2) & 3); }
+
+    // Per-lane source of each load instruction at k = 0; a K step adds k0.
+    static __device__ __forceinline__ void sources(const uint16_t *__restrict__ Ap, int64_t pa_stride,
+                                                   const uint16_t *__restrict__ Bt, int64_t pb_stride, int64_t Kp,
+                                                   int64_t m0, int64_t n0, int64_t M, int64_t N,
+                                                   const uint16_t *(&src)[LOADS]) {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int j = 0; j < LOADS; ++j) {
+            const int P = (j * NWAVES + wave) * 64 + lane;   // this lane's 16-byte slot in the stage
+            const int plane = P / PLANE_CHUNKS;
+            const int rem = P - plane * PLANE_CHUNKS;
+            const int row = rem >> 2;
+            const int c = swz(row, rem & 3);                 // logical chunk stored in this slot
+            if (row < BM) {
+                int64_t gr = m0 + row;
+                gr = gr < M ? gr : M - 1;
+                src[j] = Ap + plane * pa_stride + gr * Kp + c * 8;
+            } else {
+                int64_t gr = n0 + (row - BM);
+                gr = gr < N ? gr : N - 1;
+                src[j] = Bt + plane * pb_stride + gr * Kp + c * 8;
+            }
+        }
+    }
+
+    // Issue the loads of the K step at k0 into LDS buffer `buf`: instruction j
+    // of wave w fills the 64 slots of block j*NWAVES + w.
+    static __device__ __forceinline__ void issue(const uint16_t *const (&src)[LOADS], int64_t k0, uint16_t *buf) {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+        for (int j = 0; j < LOADS; ++j)
+            __builtin_amdgcn_global_load_lds((mm_global_void *)(src[j] + k0),
+                                             (mm_lds_void *)(buf + (j * NWAVES + wave) * 64 * 8), 16, 0, 0);
+    }
+
+    static __device__ __forceinline__ bf16x8 frag(const uint16_t *stage, int plane, int row, int q) {
+        return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(stage + plane * PLANE_CHUNKS * 8 +
+                                                                           row * 32 + swz(row, q) * 8));
+    }
+
+    static __device__ __forceinline__ void compute(const uint16_t *stage, f32x4 (&lead)[FM][FN],
+                                                   f32x4 (&corr)[FM][FN]) {
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int wm = wave / NWN, wn = wave % NWN;
+        const int li = lane & 15, q = lane >> 4;
+        bf16x8 a[NP][FM], b[NP][FN];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm) a[p][fm] = frag(stage, p, wm * WM + fm * 16 + li, q);
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) b[p][fn] = frag(stage, p, BM + wn * WN + fn * 16 + li, q);
+        }
+#pragma unroll
+        for (int t = 0; t < Terms::n; ++t)
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                for (int fn = 0; fn < FN; ++fn) {
+                    if (t == 0)
+                        lead[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0][fm], b[0][fn], lead[fm][fn], 0, 0, 0);
+                    else
+                        corr[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[Terms::pa[t]][fm], b[Terms::pb[t]][fn],
+                                                                               corr[fm][fn], 0, 0, 0);
+                }
+    }
+
+    // vmcnt(n) with the other counters left unconstrained (gfx9 encoding).
+    template <int N_>
+    static __device__ __forceinline__ void wait_vm() {
+        __builtin_amdgcn_s_waitcnt((N_ & 15) | (7 << 4) | (15 << 8) | ((N_ >> 4) << 14));
+    }
+
+    // Same contract as SplitTile::run; K must be a multiple of 32 and the
+    // plane rows K long.  vec_ok is implied by the padded layout.
+    static __device__ __forceinline__ void run(const uint16_t *__restrict__ Ap, int64_t pa_stride,
+                                               const uint16_t *__restrict__ Bt, int64_t pb_stride, void *C,
+                                               int64_t ldc, int c_is_f64, int64_t M, int64_t N, int64_t K, int64_t tm,
+                                               int64_t tn, bool, uint16_t *smem) {
+        const int64_t m0 = tm * BM, n0 = tn * BN;
+        f32x4 lead[FM][FN], corr[FM][FN];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) {
+                lead[fm][fn] = f32x4{0, 0, 0, 0};
+                corr[fm][fn] = f32x4{0, 0, 0, 0};
+            }
+        const int64_t nkt = K / BK;
+        const uint16_t *src[LOADS];
+        sources(Ap, pa_stride, Bt, pb_stride, K, m0, n0, M, N, src);
+#pragma unroll
+        for (int s = 0; s < STAGES - 1; ++s)
+            if (s < nkt) issue(src, (int64_t)s * BK, smem + s * STAGE_ELEMS);
+        for (int64_t kt = 0; kt < nkt; ++kt) {
+            // stage kt has landed once at most the later stages' loads are pending
+            const int64_t later = (nkt - 1 - kt) < (STAGES - 2) ? (nkt - 1 - kt) : (STAGES - 2);
+            if (later >= 2) wait_vm<2 * LOADS>();
+            else if (later == 1) wait_vm<LOADS>();
+            else wait_vm<0>();
+            // Every thread's part of stage kt is in LDS (the wait above) and the
+            // buffer of step kt-1 is no longer read.  A bare barrier: a fenced
+            // __syncthreads would also wait for the later stages' loads.
+            __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));   // lgkmcnt(0) only
+            __builtin_amdgcn_s_barrier();
+            if (kt + STAGES - 1 < nkt) issue(src, (kt + STAGES - 1) * BK, smem + ((kt + STAGES - 1) % STAGES) * STAGE_ELEMS);
+            compute(smem + (kt % STAGES) * STAGE_ELEMS, lead, corr);
+        }
+        // binary64 recombination of the two accumulator sets
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int wm = wave / NWN, wn = wave % NWN;
+        const int li = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t r = m0 + wm * WM + fm * 16 + q * 4 + v;
+                    const int64_t c = n0 + wn * WN + fn * 16 + li;
+                    if (r < M && c < N) {
+                        const double val = (double)lead[fm][fn][v] + (double)corr[fm][fn][v];
+                        if (c_is_f64) ((double *)C)[r * ldc + c] = val;
+                        else ((float *)C)[r * ldc + c] = (float)val;
+                    }
+                }
+        __syncthreads();   // LDS may be refilled by the next tile of a persistent workgroup
+    }
+};
+
+// Variant selector: S = 1, 2 register stages (SplitTile); S >= 3: direct-to-LDS
+// ring of S buffers (SplitTileDirect, BK = 32).
+template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool DIRECT = (S >= 3)>
+struct SplitTileSel {
+    typedef SplitTile<NPROD, BM, BN, BK, WM, WN, S> type;
+};
+template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S>
+struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, true> {
+    typedef SplitTileDirect<NPROD, BM, BN, WM, WN, S> type;
+};
+
 }  // namespace mm
