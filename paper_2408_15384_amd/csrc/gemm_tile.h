@@ -54,6 +54,9 @@ struct TileGemm {
     static constexpr int NT = NWAVES * 64;
     static constexpr int VEC = MfmaOp<T>::VEC;
     static constexpr int FM = WM / 16, FN = WN / 16, KS = BK / 4;
+    // Interleave the next slice's LDS stores with this slice's MFMAs
+    // (measured: helps the 64-cycle binary64 MFMA, hurts FP32).
+    static constexpr bool INTERLEAVE = sizeof(T) == 8;
     // Row padding (elements) keeps the 16-lane groups of an LDS read on
     // distinct banks; both keep 16-byte alignment of every row.
     static constexpr int APAD = 16 / sizeof(T);
@@ -138,7 +141,8 @@ struct TileGemm {
         }
     }
 
-    // One BK slice from LDS into the accumulators.
+    // K sub-steps [S0, S1) of one BK slice from LDS into the accumulators.
+    template <int S0, int S1>
     static __device__ __forceinline__ void compute(const T *As, const T *Bs, acc_t (&acc)[FM][FN]) {
         const int lane = threadIdx.x & 63;
         const int wave = threadIdx.x >> 6;
@@ -152,15 +156,17 @@ struct TileGemm {
 #pragma unroll
         for (int fn = 0; fn < FN; ++fn)
 #pragma unroll
-            for (int s = 0; s < KS; ++s)
+            for (int s = S0; s < S1; ++s)
                 b[fn][s] = Bs[(q * KS + s) * BS_LD + wn * WN + fn * 16 + li];
+        if (INTERLEAVE) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
+        for (int s = S0; s < S1; ++s)
 #pragma unroll
             for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
                 for (int fn = 0; fn < FN; ++fn)
                     acc[fm][fn] = MfmaOp<T>::mma(a[fm].v[s], b[fn][s], acc[fm][fn]);
+        if (INTERLEAVE) __builtin_amdgcn_s_setprio(0);
     }
 
     // The whole tile (tm, tn): C[tm*BM.., tn*BN..] = A[tm*BM.., :] . B[:, tn*BN..].
@@ -197,11 +203,23 @@ struct TileGemm {
                 load_b(rb, Bb, ldb, cols_left, K, (kt + 1) * BK, vec_ok);
             }
             const T *cur = smem + (kt & 1) * STAGE;
-            compute(cur, cur + A_STAGE, acc);
-            if (more) {
-                T *nxt = smem + ((kt + 1) & 1) * STAGE;
-                store_a(nxt, ra);
-                store_b(nxt + A_STAGE, rb);
+            T *nxt = smem + ((kt + 1) & 1) * STAGE;
+            if (INTERLEAVE) {
+                // binary64: the next slice is written to the other LDS buffer
+                // between the two halves of this slice's MFMAs, so the stores
+                // overlap matrix work (the MFMA bursts run at raised priority)
+                compute<0, KS / 2>(cur, cur + A_STAGE, acc);
+                if (more) {
+                    store_a(nxt, ra);
+                    store_b(nxt + A_STAGE, rb);
+                }
+                compute<KS / 2, KS>(cur, cur + A_STAGE, acc);
+            } else {
+                compute<0, KS>(cur, cur + A_STAGE, acc);
+                if (more) {
+                    store_a(nxt, ra);
+                    store_b(nxt + A_STAGE, rb);
+                }
             }
             __syncthreads();
         }
