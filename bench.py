@@ -333,6 +333,54 @@ def serving_section(torch, mm, wl=None, slots=4, max_batch=64, budget=64 << 30, 
     return res
 
 
+# The paper's serial timings at -O3 (Tables I and II) and its 16-thread
+# timings (section VI text), seconds, Cirrus Xeon E5-2695 2.1 GHz: context only.
+PAPER_SERIAL_O3 = {"gcc": {32: 0.00003, 64: 0.00026, 128: 0.00228, 256: 0.02028, 512: 0.17037, 1024: 1.69891},
+                   "intel": {32: 0.00003, 64: 0.00027, 128: 0.00215, 256: 0.02081, 512: 0.18232, 1024: 1.55254}}
+PAPER_16_THREADS = {"gcc": {32: 2.8e-5, 1024: 0.88}, "intel": {32: 1.57e-5, 1024: 0.12}}
+
+
+def paper_section(torch, mm, sizes=(32, 64, 128, 256, 512, 1024), reps=15):
+    """The paper's experiment on this machine: Box-Muller N(0,1) inputs at its
+    sizes, the product timed as the mean of 15 runs, on the GPU (binary64) and
+    with the CPU oracle on one host core and on all of them; each GPU result
+    checked against the oracle's per-entry bound."""
+    import oracle
+    cores = len(os.sched_getaffinity(0))
+    out = []
+    n0 = oracle.get_threads()
+    for n in sizes:
+        A, B = I.pair("normal_f64", n, n, n, seed=0)
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        dC = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        wall, ev, med, mn = timed_steps(torch, lambda: mm.gemm_f64(dA, dB, dC), reps, 3)
+        C = dC.cpu().numpy()
+        row = {"n": n, "gpu_s": ev * 1e-3, "gpu_tflops": 2.0 * n ** 3 / (ev * 1e-3) / 1e12}
+        for threads in (1, cores):
+            oracle.set_threads(threads)
+            r = reps if (threads > 1 or n <= 256) else max(1, 15 * 256 ** 3 // n ** 3)
+            ts = []
+            for _ in range(r):
+                t0 = time.perf_counter()
+                R = oracle.gemm(A, B)
+                ts.append(time.perf_counter() - t0)
+            row[f"oracle_{threads}t_s"] = float(np.mean(ts))
+            row[f"oracle_{threads}t_reps"] = r
+        bound = oracle.elementwise_bound(oracle.abs_product(A, B), n, oracle.U_F64)
+        row["max_err_over_bound"] = float((np.abs(C - R) / np.maximum(bound, 1e-300)).max())
+        row["paper_gcc_O3_serial_s"] = PAPER_SERIAL_O3["gcc"][n]
+        row["paper_intel_O3_serial_s"] = PAPER_SERIAL_O3["intel"][n]
+        if n in PAPER_16_THREADS["intel"]:
+            row["paper_intel_16t_s"] = PAPER_16_THREADS["intel"][n]
+            row["paper_gcc_16t_s"] = PAPER_16_THREADS["gcc"][n]
+        log(f"  paper sizes n={n}: gpu {row['gpu_s']*1e6:.1f} us, oracle 1 core {row['oracle_1t_s']:.4g} s, "
+            f"{cores} cores {row[f'oracle_{cores}t_s']:.4g} s, paper gcc -O3 {row['paper_gcc_O3_serial_s']} s")
+        out.append(row)
+    oracle.set_threads(n0)
+    return {"inputs": "Box-Muller N(0,1), seed 0", "cores": cores, "reps": reps,
+            "note": "serial oracle runs above 256 use fewer repetitions (oracle_1t_reps)", "rows": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -340,7 +388,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--sections", default="precision,grouped,serving",
-                    help="comma list of sections to run after the headline (precision, grouped, serving, or none)")
+                    help="comma list of sections to run after the headline (precision, grouped, serving, paper; "
+                         "or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -405,6 +454,9 @@ def main():
     if "serving" in sections:
         log("serving: 10,000 requests")
         line["serving"] = serving_section(torch, mm)
+    if "paper" in sections:
+        log("paper sizes: Box-Muller inputs, 32..1024")
+        line["paper_sizes"] = paper_section(torch, mm)
     line["paper_context"] = {"note": "the paper's own CPU timings (Cirrus, Xeon E5-2695 2.1 GHz, 18 cores), "
                                      "context only", "serial_O3_gcc_1024_s": 1.69891,
                              "intel_16_threads_1024_s": 0.12}

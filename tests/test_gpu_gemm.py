@@ -234,6 +234,14 @@ def test_residual_float_inputs(mm):
     assert np.sqrt(r2 / z2) < 1e-6
 
 
+@pytest.mark.parametrize("n", [32, 64, 128, 256, 512, 1024])
+def test_f64_paper_sizes_box_muller(mm, n):
+    """The paper's sizes with its N(0,1) Box-Muller inputs."""
+    A, B = I.pair("normal_f64", n, n, n, seed=n)
+    C = host(mm.gemm_f64(dev(A), dev(B)))
+    assert_within_bound(C, A, B, oracle.U_F64)
+
+
 # ------------------------------------------------------------------ full size
 
 @pytest.mark.parametrize("kind", ["uniform_f64", "int_f64"])
