@@ -333,6 +333,25 @@ def serving_section(torch, mm, wl=None, slots=4, max_batch=64, budget=64 << 30, 
     return res
 
 
+def layouts_section(torch, mm, n=8192, reps=5):
+    """binary64 C = op(A).op(B) at n for every operand orientation: the cost of
+    transposed storage (transpose into workspace + the row-major kernel)."""
+    A, B = I.pair("uniform_f64", n, n, n, seed=0)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    del A, B
+    C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ws = torch.empty(mm.lib().mm_gemm_ex_workspace_bytes(0, 1, 1, n, n, n), dtype=torch.uint8, device="cuda")
+    out = {}
+    for ops in ("NN", "NT", "TN", "TT"):
+        wall, ev, med, mn = timed_steps(torch, lambda: mm.gemm_ex("f64", dA, dB, ops[0], ops[1], C=C, workspace=ws),
+                                        reps, 2)
+        out[ops] = {"ms": ev, "tflops": 2.0 * n ** 3 / (ev * 1e-3) / 1e12}
+        log(f"  layout {ops}: {ev:.3f} ms {out[ops]['tflops']:.2f} TFLOP/s")
+    del dA, dB, C, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 # The paper's serial timings at -O3 (Tables I and II) and its 16-thread
 # timings (section VI text), seconds, Cirrus Xeon E5-2695 2.1 GHz: context only.
 PAPER_SERIAL_O3 = {"gcc": {32: 0.00003, 64: 0.00026, 128: 0.00228, 256: 0.02028, 512: 0.17037, 1024: 1.69891},
@@ -387,8 +406,8 @@ def main():
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--sections", default="precision,grouped,serving",
-                    help="comma list of sections to run after the headline (precision, grouped, serving, paper; "
+    ap.add_argument("--sections", default="precision,grouped,serving,layouts,paper",
+                    help="comma list of sections to run after the headline (precision, grouped, serving, layouts, paper; "
                          "or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -454,6 +473,9 @@ def main():
     if "serving" in sections:
         log("serving: 10,000 requests")
         line["serving"] = serving_section(torch, mm)
+    if "layouts" in sections:
+        log("layouts: transposed operands at N=8192")
+        line["layouts"] = layouts_section(torch, mm)
     if "paper" in sections:
         log("paper sizes: Box-Muller inputs, 32..1024")
         line["paper_sizes"] = paper_section(torch, mm)

@@ -156,6 +156,36 @@ mm_status mm_residual_f64(int64_t M, int64_t N, int64_t K,
                           void *workspace, size_t workspace_bytes, void *stream);
 
 /* ------------------------------------------------------------------------ */
+/* Transposed operands.                                                      */
+/* ------------------------------------------------------------------------ */
+
+/* op(X) = X (MM_OP_N) or X^T (MM_OP_T). */
+typedef enum mm_op { MM_OP_N = 0, MM_OP_T = 1 } mm_op;
+
+/* Bytes of device workspace mm_gemm_ex needs (0 when none). */
+size_t mm_gemm_ex_workspace_bytes(mm_method method, mm_op opa, mm_op opb, int64_t M, int64_t N, int64_t K);
+
+/*
+ * mm_gemm_ex -- C = op(A).op(B), the same product with either operand stored
+ * transposed (the storage remark of section III: a column-major operand is
+ * the row-major transpose).  All buffers row-major; op(A) is M x K and op(B)
+ * is K x N, so A is M x K (lda >= K) for MM_OP_N and K x M (lda >= M) for
+ * MM_OP_T; B is K x N (ldb >= N) for MM_OP_N and N x K (ldb >= K) for MM_OP_T.
+ * C is M x N: binary64 for MM_F64, FP32 otherwise.  binary64/FP32: a
+ * transposed operand is first transposed into the workspace, then the
+ * product runs as mm_gemm_f64/f32 (same kernels, same result bits as on
+ * explicitly transposed inputs).  Split methods: the split pass writes the
+ * planes in the orientation the kernel reads, whatever the operand's storage.
+ * workspace: device, >= mm_gemm_ex_workspace_bytes(...), or NULL to let the
+ * library allocate it stream-ordered.  A whole column-major product
+ * C = A.B (Fortran storage) is mm_gemm_* on the row-major transposes:
+ * C^T = B^T.A^T, i.e. swap A with B and M with N.
+ */
+mm_status mm_gemm_ex(mm_method method, mm_op opa, mm_op opb, int64_t M, int64_t N, int64_t K,
+                     const void *A, int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* ------------------------------------------------------------------------ */
 /* Grouped products: many independent C_i = A_i.B_i of different shapes in   */
 /* one persistent kernel launch.                                             */
 /* ------------------------------------------------------------------------ */

@@ -72,6 +72,8 @@ EXPORTS = [
     ("mm_split_bf16", _st, [_i64, _i64, _p, _i64, _i32, _i32, _p, _i64, _p]),
     ("mm_split_workspace_bytes", _sz, [_i64, _i64, _i64, _i32]),
     ("mm_gemm_split_bf16", _st, [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i32, _i32, _p, _sz, _p]),
+    ("mm_gemm_ex_workspace_bytes", _sz, [_st, _st, _st, _i64, _i64, _i64]),
+    ("mm_gemm_ex", _st, [_st, _st, _st, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _sz, _p]),
     ("mm_residual_workspace_bytes", _sz, [_i64, _i64, _i64]),
     ("mm_residual_f64", _st, [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i32, _i32, _p, _p, _p, _sz, _p]),
     ("mm_gemm_grouped", _st, [ctypes.POINTER(Problem), _i32, _st, ctypes.POINTER(_p), _p]),
@@ -216,6 +218,37 @@ def gemm_split_bf16(A, B, nprod: int = 6, C=None, out_dtype=None, workspace=None
                                    C.data_ptr(), _ld(C, "C"), int(C.dtype == torch.float64), nprod,
                                    ws_ptr or None, ws_bytes, _stream(stream)))
     return C
+
+
+def gemm_ex(method, A, B, opa: str = "N", opb: str = "N", C=None, workspace=None, stream=None):
+    """C = op(A).op(B) with op 'N' (as stored) or 'T' (transposed), mm_gemm_ex.
+    A and B are the stored (row-major) tensors."""
+    import torch
+    m = METHODS.get(method, method)
+    ta, tb = int(opa.upper() == "T"), int(opb.upper() == "T")
+    M, K = (A.shape[1], A.shape[0]) if ta else (A.shape[0], A.shape[1])
+    K2, N = (B.shape[1], B.shape[0]) if tb else (B.shape[0], B.shape[1])
+    if K != K2:
+        raise ValueError("inner dimensions differ")
+    M, N, K = int(M), int(N), int(K)
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float64 if m == MM_F64 else torch.float32, device=A.device)
+    ws_ptr, ws_bytes = 0, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    check(lib().mm_gemm_ex(m, ta, tb, M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
+                           C.data_ptr(), _ld(C, "C"), ws_ptr or None, ws_bytes, _stream(stream)))
+    return C
+
+
+def gemm_colmajor_f64(A_cm, B_cm, M: int, N: int, K: int, C_cm=None, stream=None):
+    """Column-major (Fortran-order) binary64 C = A.B on flat device buffers of
+    M*K, K*N and M*N elements: computed as the row-major C^T = B^T.A^T."""
+    import torch
+    if C_cm is None:
+        C_cm = torch.empty(M * N, dtype=torch.float64, device=A_cm.device)
+    gemm_f64(B_cm.view(N, K), A_cm.view(K, M), C_cm.view(N, M), stream=stream)
+    return C_cm
 
 
 def residual_f64(A, B, C, x, out=None, workspace=None, stream=None):

@@ -213,13 +213,7 @@ static mm_status run_split(int variant, int64_t M, int64_t N, int64_t K, const f
     } else if (workspace_bytes < need) {
         return fail(MM_E_INVAL, "workspace too small");
     }
-    const int np = nprod == 3 ? 2 : 3;
-    uint16_t *Ap = (uint16_t *)ws;
-    uint16_t *Bt = (uint16_t *)((char *)ws + split_b_offset_bytes(M, K, nprod));
-    const int64_t Kp = split_padded_k(K);
-    hipError_t e = launch_split(M, K, A, lda, np, 0, Ap, M * Kp, Kp, st);
-    if (e == hipSuccess) e = launch_split(K, N, B, ldb, np, 1, Bt, N * Kp, Kp, st);
-    if (e == hipSuccess) e = launch_gemm_split(variant, nprod, M, N, Kp, Ap, Bt, C, ldc, c_is_f64, st);
+    hipError_t e = launch_split_product(variant, nprod, 0, 0, M, N, K, A, lda, B, ldb, C, ldc, c_is_f64, ws, st);
     if (owned) {
         hipError_t e2 = hipFreeAsync(ws, st);
         if (e == hipSuccess) e = e2;
@@ -239,6 +233,91 @@ mm_status mm_gemm_split_bf16(int64_t M, int64_t N, int64_t K, const float *A, in
     const mm_method m = nprod == 3 ? MM_SPLIT_BF16_3 : MM_SPLIT_BF16_6;
     return run_split(select_variant(m, M, N, K), M, N, K, A, lda, B, ldb, C, ldc, c_is_f64, nprod, workspace,
                      workspace_bytes, (hipStream_t)stream);
+    MM_GUARD_END
+}
+
+size_t mm_gemm_ex_workspace_bytes(mm_method method, mm_op opa, mm_op opb, int64_t M, int64_t N, int64_t K) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (method == MM_SPLIT_BF16_3 || method == MM_SPLIT_BF16_6)
+        return split_workspace_bytes(M, N, K, method == MM_SPLIT_BF16_3 ? 3 : 6);
+    const size_t e = method == MM_F64 ? 8 : 4;
+    size_t b = 0;
+    if (opa == MM_OP_T) b += ((size_t)M * K * e + 255) & ~(size_t)255;
+    if (opb == MM_OP_T) b += (size_t)K * N * e;
+    return b;
+}
+
+mm_status mm_gemm_ex(mm_method method, mm_op opa, mm_op opb, int64_t M, int64_t N, int64_t K, const void *A,
+                     int64_t lda, const void *B, int64_t ldb, void *C, int64_t ldc, void *workspace,
+                     size_t workspace_bytes, void *stream) {
+    MM_GUARD_BEGIN
+    if ((opa != MM_OP_N && opa != MM_OP_T) || (opb != MM_OP_N && opb != MM_OP_T))
+        return fail(MM_E_INVAL, "op must be MM_OP_N or MM_OP_T");
+    if (method < MM_F64 || method > MM_SPLIT_BF16_6) return fail(MM_E_INVAL, "unknown method");
+    const size_t e = method == MM_F64 ? 8 : 4;
+    if (M < 0 || N < 0 || K < 0) return fail(MM_E_INVAL, "negative dimension");
+    // stored shapes: A is (M x K) or (K x M), B is (K x N) or (N x K)
+    const int64_t ar = opa ? K : M, ac = opa ? M : K, br = opb ? N : K, bc = opb ? K : N;
+    if (lda < (ac > 1 ? ac : 1)) return fail(MM_E_INVAL, "lda smaller than a stored row of A");
+    if (ldb < (bc > 1 ? bc : 1)) return fail(MM_E_INVAL, "ldb smaller than a stored row of B");
+    if (ldc < (N > 1 ? N : 1)) return fail(MM_E_INVAL, "ldc < max(N,1)");
+    if (M == 0 || N == 0) return MM_OK;
+    if (!C) return fail(MM_E_INVAL, "C is NULL");
+    if (K > 0 && (!A || !B)) return fail(MM_E_INVAL, "A or B is NULL");
+    const size_t cb = span_bytes(M, N, ldc, e);
+    if (K > 0 && (overlaps(C, cb, A, span_bytes(ar, ac, lda, e)) || overlaps(C, cb, B, span_bytes(br, bc, ldb, e))))
+        return fail(MM_E_INVAL, "C overlaps A or B");
+    mm_status s = check_arch();
+    if (s != MM_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if (K == 0) {
+        MM_HIP(launch_fill_zero(C, M, N, ldc, (int)e, st));
+        return MM_OK;
+    }
+    const size_t need = mm_gemm_ex_workspace_bytes(method, opa, opb, M, N, K);
+    void *ws = workspace;
+    bool owned = false;
+    if (need && !ws) {
+        MM_HIP(hipMallocAsync(&ws, need, st));
+        owned = true;
+    } else if (need && workspace_bytes < need) {
+        return fail(MM_E_INVAL, "workspace too small");
+    }
+    hipError_t err = hipSuccess;
+    if (method == MM_SPLIT_BF16_3 || method == MM_SPLIT_BF16_6) {
+        const int nprod = method == MM_SPLIT_BF16_3 ? 3 : 6;
+        err = launch_split_product(select_variant(method, M, N, K), nprod, opa, opb, M, N, K, (const float *)A, lda,
+                                   (const float *)B, ldb, C, ldc, 0, ws, st);
+    } else {
+        // transposed operands are brought to row-major op(X) in the workspace
+        const void *a = A, *b = B;
+        int64_t la = lda, lb = ldb;
+        char *p = (char *)ws;
+        if (opa == MM_OP_T) {
+            err = launch_transpose(A, lda, K, M, p, K, (int)e, st);
+            a = p;
+            la = K;
+            p += ((size_t)M * K * e + 255) & ~(size_t)255;
+        }
+        if (err == hipSuccess && opb == MM_OP_T) {
+            err = launch_transpose(B, ldb, N, K, p, N, (int)e, st);
+            b = p;
+            lb = N;
+        }
+        if (err == hipSuccess) {
+            const int v = select_variant(method, M, N, K);
+            err = method == MM_F64 ? launch_gemm_f64(v, M, N, K, (const double *)a, la, (const double *)b, lb,
+                                                     (double *)C, ldc, st)
+                                   : launch_gemm_f32(v, M, N, K, (const float *)a, la, (const float *)b, lb,
+                                                     (float *)C, ldc, st);
+        }
+    }
+    if (owned) {
+        hipError_t e2 = hipFreeAsync(ws, st);
+        if (err == hipSuccess) err = e2;
+    }
+    if (err != hipSuccess) return hip_fail(err, "mm_gemm_ex launch");
+    return MM_OK;
     MM_GUARD_END
 }
 

@@ -67,6 +67,40 @@ hipError_t launch_gemm_f32(int variant, int64_t M, int64_t N, int64_t K, const f
     }
 }
 
+// ---------------------------------------------------------------- transpose
+// 64 x 64 tiles through LDS: reads along rows of X, writes along rows of X^T.
+template <typename T>
+__global__ __launch_bounds__(256) void transpose_kernel(const T *__restrict__ X, int64_t ldx, int64_t rows,
+                                                        int64_t cols, T *__restrict__ Y, int64_t ldy) {
+    __shared__ T tile[64][65];
+    const int64_t tiles_c = (cols + 63) / 64;
+    const int64_t r0 = (blockIdx.x / tiles_c) * 64, c0 = (blockIdx.x % tiles_c) * 64;
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    for (int i = ty; i < 64; i += 4) {
+        const int64_t r = r0 + i, c = c0 + tx;
+        if (r < rows && c < cols) tile[i][tx] = X[r * ldx + c];
+    }
+    __syncthreads();
+    for (int j = ty; j < 64; j += 4) {
+        const int64_t c = c0 + j, r = r0 + tx;
+        if (c < cols && r < rows) Y[c * ldy + r] = tile[tx][j];
+    }
+}
+
+hipError_t launch_transpose(const void *X, int64_t ldx, int64_t rows, int64_t cols, void *Y, int64_t ldy,
+                            int elem_bytes, hipStream_t stream) {
+    if (rows <= 0 || cols <= 0) return hipSuccess;
+    const int64_t blocks = ((rows + 63) / 64) * ((cols + 63) / 64);
+    if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    if (elem_bytes == 8)
+        hipLaunchKernelGGL(transpose_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, stream, (const double *)X,
+                           ldx, rows, cols, (double *)Y, ldy);
+    else
+        hipLaunchKernelGGL(transpose_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, stream, (const float *)X,
+                           ldx, rows, cols, (float *)Y, ldy);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- zero fill
 // C := 0 for K == 0 (the empty sum).  A kernel rather than a memset so the
 // call can sit inside a captured graph.

@@ -73,6 +73,15 @@ hipError_t launch_residual(int64_t M, int64_t N, int64_t K, const void *A, int64
                            int64_t ldb, const void *C, int64_t ldc, int in_dtype, int c_dtype, const double *x,
                            double *out, void *ws, hipStream_t stream);
 
+// Y (cols x rows, leading dim ldy) = X^T for X rows x cols (leading dim ldx).
+hipError_t launch_transpose(const void *X, int64_t ldx, int64_t rows, int64_t cols, void *Y, int64_t ldy,
+                            int elem_bytes, hipStream_t stream);
+
+// Split pass + split GEMM for operands in any orientation (planes in ws).
+hipError_t launch_split_product(int variant, int nprod, int opa, int opb, int64_t M, int64_t N, int64_t K,
+                                const float *A, int64_t lda, const float *B, int64_t ldb, void *C, int64_t ldc,
+                                int c_is_f64, void *ws, hipStream_t st);
+
 // Zero-fill of an M x N matrix (K == 0 products).
 hipError_t launch_fill_zero(void *C, int64_t M, int64_t N, int64_t ldc, int elem_bytes, hipStream_t stream);
 

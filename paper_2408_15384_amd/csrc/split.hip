@@ -89,6 +89,24 @@ hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx,
 
 int64_t split_padded_k(int64_t K) { return (K + 31) / 32 * 32; }
 
+hipError_t launch_split_product(int variant, int nprod, int opa, int opb, int64_t M, int64_t N, int64_t K,
+                                const float *A, int64_t lda, const float *B, int64_t ldb, void *C, int64_t ldc,
+                                int c_is_f64, void *ws, hipStream_t st) {
+    const int np = nprod == 3 ? 2 : 3;
+    const int64_t Kp = split_padded_k(K);
+    uint16_t *Ap = (uint16_t *)ws;
+    uint16_t *Bt = (uint16_t *)((char *)ws + split_b_offset_bytes(M, K, nprod));
+    // A planes are M x Kp: rows of A as stored (N), or the transpose of K x M (T)
+    hipError_t e = opa ? launch_split(K, M, A, lda, np, 1, Ap, M * Kp, Kp, st)
+                       : launch_split(M, K, A, lda, np, 0, Ap, M * Kp, Kp, st);
+    // B planes are N x Kp: the transpose of K x N (N), or rows of B as stored (T)
+    if (e == hipSuccess)
+        e = opb ? launch_split(N, K, B, ldb, np, 0, Bt, N * Kp, Kp, st)
+                : launch_split(K, N, B, ldb, np, 1, Bt, N * Kp, Kp, st);
+    if (e == hipSuccess) e = launch_gemm_split(variant, nprod, M, N, Kp, Ap, Bt, C, ldc, c_is_f64, st);
+    return e;
+}
+
 // Planes of the product use rows of split_padded_k(K) elements (zero tail):
 // every 8-element fragment is one aligned 16-byte access and every 32-wide K
 // step is whole.
