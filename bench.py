@@ -333,6 +333,26 @@ def serving_section(torch, mm, wl=None, slots=4, max_batch=64, budget=64 << 30, 
     return res
 
 
+def strassen_section(torch, mm, n=8192, reps=5):
+    """binary64 at n by one Strassen-Winograd level: time, throughput counted
+    as the definition's 2n^3, and the normwise error of sampled rows against
+    the oracle's product."""
+    import oracle
+    A, B = I.pair("uniform_f64", n, n, n, seed=0)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ws = torch.empty(mm.lib().mm_strassen_workspace_bytes(n, n, n), dtype=torch.uint8, device="cuda")
+    wall, ev, med, mn = timed_steps(torch, lambda: mm.gemm_strassen_f64(dA, dB, C=C, workspace=ws), reps, 2)
+    Ch = C[:8].cpu().numpy()
+    R = oracle.gemm(A[:8], B)
+    out = {"ms": ev, "tflops_equiv": 2.0 * n ** 3 / (ev * 1e-3) / 1e12,
+           "normwise_err_vs_oracle_rows0_7": float(np.linalg.norm(Ch - R) / np.linalg.norm(R))}
+    log(f"  strassen: {ev:.3f} ms {out['tflops_equiv']:.2f} TFLOP/s-equivalent err {out['normwise_err_vs_oracle_rows0_7']:.2e}")
+    del dA, dB, C, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def layouts_section(torch, mm, n=8192, reps=5):
     """binary64 C = op(A).op(B) at n for every operand orientation: the cost of
     transposed storage (transpose into workspace + the row-major kernel)."""
@@ -406,8 +426,9 @@ def main():
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--sections", default="precision,grouped,serving,layouts,paper",
-                    help="comma list of sections to run after the headline (precision, grouped, serving, layouts, paper; "
+    ap.add_argument("--sections", default="precision,grouped,serving,strassen,layouts,paper",
+                    help="comma list of sections to run after the headline (precision, grouped, serving, strassen, layouts, "
+                         "paper; "
                          "or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -473,6 +494,9 @@ def main():
     if "serving" in sections:
         log("serving: 10,000 requests")
         line["serving"] = serving_section(torch, mm)
+    if "strassen" in sections:
+        log("strassen: one Strassen-Winograd level at N=8192")
+        line["strassen"] = strassen_section(torch, mm)
     if "layouts" in sections:
         log("layouts: transposed operands at N=8192")
         line["layouts"] = layouts_section(torch, mm)

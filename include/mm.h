@@ -155,6 +155,30 @@ mm_status mm_residual_f64(int64_t M, int64_t N, int64_t K,
                           const double *x, double *out,
                           void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * mm_gemm_strassen_f64 -- C = A.B in binary64 by one level of Strassen's
+ * scheme in Winograd's form (the sub-cubic method cited in the paper's
+ * literature review): A and B are split in 2 x 2 quadrants and C is formed
+ * from seven half-size binary64 products (mm_gemm_f64's kernels) and fifteen
+ * quadrant additions, in the fixed order
+ *   S1 = A21 + A22, S2 = S1 - A11, S3 = A11 - A21, S4 = A12 - S2,
+ *   T1 = B12 - B11, T2 = B22 - T1, T3 = B22 - B12, T4 = T2 - B21,
+ *   P1 = A11 B11, P2 = A12 B21, P3 = S4 B22, P4 = A22 T4, P5 = S1 T1,
+ *   P6 = S2 T2, P7 = S3 T3,
+ *   C11 = P1 + P2, C12 = ((P1 + P6) + P5) + P3, C21 = ((P1 + P6) + P7) - P4,
+ *   C22 = ((P1 + P6) + P7) + P5.
+ * 7/8 of the multiplications of the definition; the error bound is normwise
+ * rather than per entry (exact when every intermediate is representable, e.g.
+ * small integers).  M, N and K must be even (otherwise MM_E_UNSUPPORTED).
+ * workspace: device, >= mm_strassen_workspace_bytes(M, N, K) bytes
+ * (8 * (M*K + K*N + 7*M*N/4)), or NULL for stream-ordered allocation.
+ */
+size_t mm_strassen_workspace_bytes(int64_t M, int64_t N, int64_t K);
+mm_status mm_gemm_strassen_f64(int64_t M, int64_t N, int64_t K,
+                               const double *A, int64_t lda, const double *B, int64_t ldb,
+                               double *C, int64_t ldc, void *workspace, size_t workspace_bytes,
+                               void *stream);
+
 /* ------------------------------------------------------------------------ */
 /* Transposed operands.                                                      */
 /* ------------------------------------------------------------------------ */

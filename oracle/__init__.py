@@ -215,3 +215,73 @@ def normwise_rel(C, R) -> float:
     d = np.linalg.norm((C - R).ravel())
     n = np.linalg.norm(R.ravel())
     return float(d / n) if n else float(d)
+
+
+# ---------------------------------------------------------------------------
+# One level of Strassen's scheme in Winograd's form (the sub-cubic family the
+# paper cites in its literature review).  With A, B split in 2 x 2 quadrants
+# (M, N, K even):
+#   S1 = A21 + A22, S2 = S1 - A11, S3 = A11 - A21, S4 = A12 - S2
+#   T1 = B12 - B11, T2 = B22 - T1, T3 = B22 - B12, T4 = T2 - B21
+#   P1 = A11 B11, P2 = A12 B21, P3 = S4 B22, P4 = A22 T4,
+#   P5 = S1 T1,  P6 = S2 T2,   P7 = S3 T3
+#   U1 = P1 + P2, U2 = P1 + P6, U3 = U2 + P7, U4 = U2 + P5,
+#   U5 = U4 + P3, U6 = U3 - P4, U7 = U3 + P5
+#   C11 = U1, C12 = U5, C21 = U6, C22 = U7
+# Every sum is one binary64 rounding in this order; the seven products are the
+# definitional loop (``gemm``).
+# ---------------------------------------------------------------------------
+
+def strassen_parts(A, B):
+    """The operands of the seven products, in order P1..P7, as (X, Y) pairs."""
+    A = _as_f64(A)
+    B = _as_f64(B)
+    M, K = A.shape
+    N = B.shape[1]
+    if M % 2 or N % 2 or K % 2:
+        raise ValueError("one Strassen level needs even M, N, K")
+    m, k, n = M // 2, K // 2, N // 2
+    A11, A12, A21, A22 = A[:m, :k], A[:m, k:], A[m:, :k], A[m:, k:]
+    B11, B12, B21, B22 = B[:k, :n], B[:k, n:], B[k:, :n], B[k:, n:]
+    S1 = A21 + A22
+    S2 = S1 - A11
+    S3 = A11 - A21
+    S4 = A12 - S2
+    T1 = B12 - B11
+    T2 = B22 - T1
+    T3 = B22 - B12
+    T4 = T2 - B21
+    return [(A11, B11), (A12, B21), (S4, B22), (A22, T4), (S1, T1), (S2, T2), (S3, T3)]
+
+
+def strassen_combine(P):
+    """C from the seven products P1..P7 (Winograd's U-sequence)."""
+    P1, P2, P3, P4, P5, P6, P7 = P
+    U1 = P1 + P2
+    U2 = P1 + P6
+    U3 = U2 + P7
+    U4 = U2 + P5
+    U5 = U4 + P3
+    U6 = U3 - P4
+    U7 = U3 + P5
+    return np.block([[U1, U5], [U6, U7]])
+
+
+def strassen(A, B):
+    """One Strassen-Winograd level with every product by ``gemm``."""
+    return strassen_combine([gemm(X, Y) for X, Y in strassen_parts(A, B)])
+
+
+def strassen_product_bound(A, B):
+    """Per-entry bound on the difference between two evaluations of the
+    scheme whose seven products each lie within 4*k*u*(|X||Y|) of exact (k the
+    inner size), the sums being evaluated identically: the bound is carried
+    through the U-sequence (each U adds the bounds of its terms), with a 1%
+    margin for the roundings of the sums."""
+    parts = strassen_parts(A, B)
+    k = parts[0][0].shape[1]
+    b = [elementwise_bound(gemm(np.abs(X), np.abs(Y)), k, U_F64) for X, Y in parts]
+    b1, b2, b3, b4, b5, b6, b7 = b
+    u2 = b1 + b6
+    u3 = u2 + b7
+    return 1.01 * np.block([[b1 + b2, u2 + b5 + b3], [u3 + b4, u3 + b5]])

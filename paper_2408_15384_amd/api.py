@@ -72,6 +72,8 @@ EXPORTS = [
     ("mm_split_bf16", _st, [_i64, _i64, _p, _i64, _i32, _i32, _p, _i64, _p]),
     ("mm_split_workspace_bytes", _sz, [_i64, _i64, _i64, _i32]),
     ("mm_gemm_split_bf16", _st, [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i32, _i32, _p, _sz, _p]),
+    ("mm_strassen_workspace_bytes", _sz, [_i64, _i64, _i64]),
+    ("mm_gemm_strassen_f64", _st, [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _sz, _p]),
     ("mm_gemm_ex_workspace_bytes", _sz, [_st, _st, _st, _i64, _i64, _i64]),
     ("mm_gemm_ex", _st, [_st, _st, _st, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _sz, _p]),
     ("mm_residual_workspace_bytes", _sz, [_i64, _i64, _i64]),
@@ -217,6 +219,20 @@ def gemm_split_bf16(A, B, nprod: int = 6, C=None, out_dtype=None, workspace=None
     check(lib().mm_gemm_split_bf16(M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
                                    C.data_ptr(), _ld(C, "C"), int(C.dtype == torch.float64), nprod,
                                    ws_ptr or None, ws_bytes, _stream(stream)))
+    return C
+
+
+def gemm_strassen_f64(A, B, C=None, workspace=None, stream=None):
+    """C = A.B in binary64 by one Strassen-Winograd level (mm_gemm_strassen_f64)."""
+    import torch
+    M, N, K = _shapes(A, B)
+    if C is None:
+        C = torch.empty((M, N), dtype=torch.float64, device=A.device)
+    ws_ptr, ws_bytes = 0, 0
+    if workspace is not None:
+        ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    check(lib().mm_gemm_strassen_f64(M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"),
+                                     C.data_ptr(), _ld(C, "C"), ws_ptr or None, ws_bytes, _stream(stream)))
     return C
 
 

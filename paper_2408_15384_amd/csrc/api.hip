@@ -321,6 +321,43 @@ mm_status mm_gemm_ex(mm_method method, mm_op opa, mm_op opb, int64_t M, int64_t 
     MM_GUARD_END
 }
 
+size_t mm_strassen_workspace_bytes(int64_t M, int64_t N, int64_t K) {
+    if (M <= 0 || N <= 0 || K <= 0 || M % 2 || N % 2 || K % 2) return 0;
+    return strassen_workspace_bytes(M, N, K);
+}
+
+mm_status mm_gemm_strassen_f64(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
+                               int64_t ldb, double *C, int64_t ldc, void *workspace, size_t workspace_bytes,
+                               void *stream) {
+    MM_GUARD_BEGIN
+    mm_status s = check_gemm_args(M, N, K, A, lda, B, ldb, C, ldc, 8, 8);
+    if (s != MM_OK || M == 0 || N == 0) return s;
+    if (M % 2 || N % 2 || K % 2) return fail(MM_E_UNSUPPORTED, "one Strassen level needs even M, N, K");
+    if ((s = check_arch()) != MM_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if (K == 0) {
+        MM_HIP(launch_fill_zero(C, M, N, ldc, 8, st));
+        return MM_OK;
+    }
+    const size_t need = strassen_workspace_bytes(M, N, K);
+    void *ws = workspace;
+    bool owned = false;
+    if (!ws) {
+        MM_HIP(hipMallocAsync(&ws, need, st));
+        owned = true;
+    } else if (workspace_bytes < need) {
+        return fail(MM_E_INVAL, "workspace too small");
+    }
+    hipError_t e = launch_strassen_f64(M, N, K, A, lda, B, ldb, C, ldc, ws, st);
+    if (owned) {
+        hipError_t e2 = hipFreeAsync(ws, st);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e != hipSuccess) return hip_fail(e, "Strassen launch");
+    return MM_OK;
+    MM_GUARD_END
+}
+
 size_t mm_residual_workspace_bytes(int64_t M, int64_t N, int64_t K) {
     if (M < 0 || N < 0 || K < 0) return 0;
     return residual_workspace_bytes(M, N, K);

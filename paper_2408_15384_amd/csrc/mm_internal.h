@@ -82,6 +82,11 @@ hipError_t launch_split_product(int variant, int nprod, int opa, int opb, int64_
                                 const float *A, int64_t lda, const float *B, int64_t ldb, void *C, int64_t ldc,
                                 int c_is_f64, void *ws, hipStream_t st);
 
+// One Strassen-Winograd level on the binary64 GEMM (M, N, K even, > 0).
+size_t strassen_workspace_bytes(int64_t M, int64_t N, int64_t K);
+hipError_t launch_strassen_f64(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
+                               int64_t ldb, double *C, int64_t ldc, void *ws, hipStream_t st);
+
 // Zero-fill of an M x N matrix (K == 0 products).
 hipError_t launch_fill_zero(void *C, int64_t M, int64_t N, int64_t ldc, int elem_bytes, hipStream_t stream);
 

@@ -241,3 +241,40 @@ def test_freivalds_exact_product_zero_and_planted_error():
     C2[3, 7] += 5.0
     r2, _ = oracle.freivalds(A, B, C2, x)
     assert r2 == (5.0 * x[7]) ** 2
+
+
+# ------------------------------------------------------------- Strassen level
+
+def test_strassen_exact_on_integers():
+    """The scheme is algebraically the product: exact whenever every
+    intermediate is representable."""
+    for (M, N, K) in [(2, 2, 2), (6, 4, 10), (64, 48, 32)]:
+        A, B = I.pair("int_f64", M, N, K, seed=M + K)
+        assert np.array_equal(oracle.strassen(A, B), oracle.gemm(A, B))
+
+
+def test_strassen_each_formula_matters():
+    """Dropping or flipping any one term of the scheme breaks exactness: the
+    integer pin sees every formula."""
+    A, B = I.pair("int_f64", 8, 8, 8, seed=21)
+    R = oracle.gemm(A, B)
+    P = [oracle.gemm(X, Y) for X, Y in oracle.strassen_parts(A, B)]
+    for i in range(7):
+        Q = list(P)
+        Q[i] = -Q[i]
+        assert not np.array_equal(oracle.strassen_combine(Q), R)
+
+
+def test_strassen_float_close_to_product():
+    A, B = I.pair("uniform_f64", 96, 80, 128, seed=22)
+    S = oracle.strassen(A, B)
+    R = oracle.gemm(A, B)
+    # normwise: a few multiples of the conventional K*u growth
+    assert oracle.normwise_rel(S, R) < 20 * 128 * oracle.U_F64
+    assert np.all(np.abs(S - R) <= oracle.strassen_product_bound(A, B) + oracle.elementwise_bound(
+        oracle.abs_product(A, B), 128, oracle.U_F64) * 4)
+
+
+def test_strassen_rejects_odd():
+    with pytest.raises(ValueError):
+        oracle.strassen(np.ones((3, 2)), np.ones((2, 2)))
