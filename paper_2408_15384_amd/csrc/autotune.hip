@@ -60,7 +60,9 @@ int default_variant(mm_method method, int64_t M, int64_t N, int64_t K) {
             return 1;
         case MM_SPLIT_BF16_3:
         case MM_SPLIT_BF16_6:
-            // direct-to-LDS 3-stage ring, 8 waves, for mid and large products
+            // direct-to-LDS rings: 256x128 (2 buffers) for large products,
+            // 128x128 (3 buffers) for mid-size ones
+            if (M >= 1024 && N >= 1024) return 9;
             if (mn >= (int64_t)512 * 512) return 6;
             return 1;
     }

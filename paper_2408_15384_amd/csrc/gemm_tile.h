@@ -57,10 +57,14 @@ struct TileGemm {
     // Interleave the next slice's LDS stores with this slice's MFMAs
     // (measured: helps the 64-cycle binary64 MFMA, hurts FP32).
     static constexpr bool INTERLEAVE = sizeof(T) == 8;
-    // Row padding (elements) keeps the 16-lane groups of an LDS read on
-    // distinct banks; both keep 16-byte alignment of every row.
+    // Row padding (elements) keeps the lane groups of an LDS read on distinct
+    // banks and every row 16-byte aligned.  A: 16 lanes read 16 rows at one
+    // offset, so the row stride is an odd multiple of 16 bytes.  B: the four
+    // lane groups read rows KS apart, which must fall 64 bytes (FP32: all 64
+    // lanes in one pass) or 128 bytes (binary64: 32 lanes per pass) apart
+    // modulo the 256-byte bank row.
     static constexpr int APAD = 16 / sizeof(T);
-    static constexpr int BPAD = 32 / sizeof(T);
+    static constexpr int BPAD = sizeof(T) == 8 ? 4 : 4;
     static constexpr int AS_LD = BK + APAD;
     static constexpr int BS_LD = BN + BPAD;
     static constexpr int A_STAGE = BM * AS_LD;

@@ -408,15 +408,15 @@ struct SplitTileDirect {
     }
 };
 
-// Variant selector: S = 1, 2 register stages (SplitTile); S >= 3: direct-to-LDS
-// ring of S buffers (SplitTileDirect, BK = 32).
-template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool DIRECT = (S >= 3)>
+// Variant selector: S = 1, 2 register stages (SplitTile); S = 10 + b: direct
+// global-to-LDS ring of b buffers (SplitTileDirect, BK = 32).
+template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool DIRECT = (S >= 10)>
 struct SplitTileSel {
     typedef SplitTile<NPROD, BM, BN, BK, WM, WN, S> type;
 };
 template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S>
 struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, true> {
-    typedef SplitTileDirect<NPROD, BM, BN, WM, WN, S> type;
+    typedef SplitTileDirect<NPROD, BM, BN, WM, WN, S - 10> type;
 };
 
 }  // namespace mm

@@ -18,7 +18,8 @@
     X(3, 128, 128, 32, 64, 64)
 
 // Split variants carry a seventh field, S: 1 or 2 register stages of global
-// prefetch, or S >= 3 LDS buffers fed by direct global-to-LDS loads (BK 32).
+// prefetch, or 10 + b: a ring of b LDS buffers fed by direct global-to-LDS
+// loads (BK 32).
 #define MM_SPLIT_VARIANTS(X)          \
     X(0, 128, 128, 32, 64, 64, 1)     \
     X(1, 64, 64, 32, 32, 32, 1)       \
@@ -26,6 +27,7 @@
     X(3, 128, 128, 32, 64, 32, 1)     \
     X(4, 128, 128, 32, 64, 32, 2)     \
     X(5, 64, 64, 32, 32, 32, 2)       \
-    X(6, 128, 128, 32, 64, 32, 3)     \
-    X(7, 128, 128, 32, 64, 64, 3)     \
-    X(8, 64, 64, 32, 32, 32, 3)
+    X(6, 128, 128, 32, 64, 32, 13)    \
+    X(7, 128, 128, 32, 64, 64, 13)    \
+    X(8, 64, 64, 32, 32, 32, 13)      \
+    X(9, 256, 128, 32, 64, 64, 12)
