@@ -276,8 +276,8 @@ int32_t mm_variant_count(mm_method method);
 mm_status mm_variant_info(mm_method method, int32_t variant, int32_t *bm, int32_t *bn, int32_t *bk);
 
 /* The variant the library will use for (method, M, N, K): the autotune cache
- * entry of the shape bucket if present, else a fixed default.  A pure
- * function of its arguments and the loaded cache. */
+ * entry of the shape bucket if present, else a fixed cost model of the shape.
+ * A pure function of its arguments and the loaded cache. */
 int32_t mm_select_variant(mm_method method, int64_t M, int64_t N, int64_t K);
 
 /* Run a single product with an explicit variant (for tuning and tests).

@@ -1,9 +1,9 @@
 // Tile-variant selection and the autotuner.
 //
-// The variant used for a product is a pure function of (method, shape bucket)
-// and the loaded cache: the bucket is (method, ceil(log2 M), ceil(log2 N),
-// ceil(log2 K)); a cache entry written by mm_autotune wins, otherwise a fixed
-// size rule applies.  Selection never depends on load or timing at call time,
+// The variant used for a product is a pure function of (method, M, N, K) and
+// the loaded cache: a cache entry written by mm_autotune for the shape's
+// bucket (method, ceil(log2 M), ceil(log2 N), ceil(log2 K)) wins, otherwise a
+// fixed cost model over the exact shape applies.  Selection never depends on load or timing at call time,
 // so the same shape always runs the same kernel (results are reproducible
 // bit for bit, alone or inside a batch).
 #include <algorithm>
@@ -45,26 +45,49 @@ Key key_of(mm_method m, int64_t M, int64_t N, int64_t K) {
     return Key((int)m, clog2(M), clog2(N), clog2(K));
 }
 
+// Default rule: a cost model over a few candidate tiles per method.  Tiles
+// are dealt round-robin over the 256 compute units, so the busiest unit
+// computes ceil(tiles / 256) of them, each at 1/256 of the rate the variant
+// sustains on a large product (measured on MI355X, in TFLOP/s of 2MNK).  The
+// model picks the candidate whose busiest unit finishes first; it charges
+// the padding of ragged edge tiles and the idle units of a small grid, which
+// is what decides between tile sizes.
+struct Candidate {
+    int variant;
+    int bm, bn;
+    double rate;
+};
+
+const Candidate kF64Cand[] = {{4, 256, 128, 65.4}, {3, 128, 64, 56.3}, {6, 64, 64, 60.8}};
+const Candidate kF32Cand[] = {{2, 256, 128, 132.2}, {3, 128, 128, 122.4}, {6, 64, 64, 107.4}};
+const Candidate kSplit3Cand[] = {{9, 256, 128, 330.0}, {6, 128, 128, 277.0}, {8, 64, 64, 217.0}};
+const Candidate kSplit6Cand[] = {{9, 256, 128, 203.7}, {6, 128, 128, 182.9}, {8, 64, 64, 120.9}};
+
+constexpr double kCUs = 256.0;
+
+template <size_t N>
+int pick(const Candidate (&c)[N], int64_t M, int64_t N_, int64_t K) {
+    int best = c[0].variant;
+    double best_t = 0;
+    for (size_t i = 0; i < N; ++i) {
+        const double tiles = (double)((M + c[i].bm - 1) / c[i].bm) * (double)((N_ + c[i].bn - 1) / c[i].bn);
+        const double per_cu = std::ceil(tiles / kCUs);
+        const double t = per_cu * 2.0 * c[i].bm * c[i].bn * (double)std::max<int64_t>(K, 1) * kCUs / c[i].rate;
+        if (i == 0 || t < best_t) {
+            best = c[i].variant;
+            best_t = t;
+        }
+    }
+    return best;
+}
+
 int default_variant(mm_method method, int64_t M, int64_t N, int64_t K) {
-    (void)K;
-    const int64_t mn = M * N;
+    if (M <= 0 || N <= 0) return 1;
     switch (method) {
-        case MM_F64:
-            // 256x128 (8 waves) for large products, 128x128 mid, 64x64 small
-            if (M >= 2048 && N >= 1024) return 2;
-            if (mn >= (int64_t)512 * 512) return 0;
-            return 1;
-        case MM_F32:
-            if (M >= 2048 && N >= 1024) return 2;
-            if (mn >= (int64_t)512 * 512) return 0;
-            return 1;
-        case MM_SPLIT_BF16_3:
-        case MM_SPLIT_BF16_6:
-            // direct-to-LDS rings: 256x128 (2 buffers) for large products,
-            // 128x128 (3 buffers) for mid-size ones
-            if (M >= 1024 && N >= 1024) return 9;
-            if (mn >= (int64_t)512 * 512) return 6;
-            return 1;
+        case MM_F64: return pick(kF64Cand, M, N, K);
+        case MM_F32: return pick(kF32Cand, M, N, K);
+        case MM_SPLIT_BF16_3: return pick(kSplit3Cand, M, N, K);
+        case MM_SPLIT_BF16_6: return pick(kSplit6Cand, M, N, K);
     }
     return 0;
 }

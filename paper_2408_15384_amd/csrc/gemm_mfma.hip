@@ -34,8 +34,8 @@ static hipError_t launch_tile(int64_t M, int64_t N, int64_t K, const T *A, int64
 }
 
 // ---------------------------------------------------------------- variants
-#define MM_COUNT(id, bm, bn, bk, wm, wn) +1
-#define MM_CFG(id, bm, bn, bk, wm, wn) case id: return TileCfg{bm, bn, bk};
+#define MM_COUNT(id, bm, bn, bk, wm, wn, st) +1
+#define MM_CFG(id, bm, bn, bk, wm, wn, st) case id: return TileCfg{bm, bn, bk};
 
 int f64_variant_count() { return 0 MM_F64_VARIANTS(MM_COUNT); }
 int f32_variant_count() { return 0 MM_F32_VARIANTS(MM_COUNT); }
@@ -46,10 +46,10 @@ TileCfg f32_variant(int v) {
     switch (v) { MM_F32_VARIANTS(MM_CFG) default: return TileCfg{0, 0, 0}; }
 }
 
-#define MM_LAUNCH_F64(id, bm, bn, bk, wm, wn) \
-    case id: return launch_tile<TileGemm<double, bm, bn, bk, wm, wn>, double>(M, N, K, A, lda, B, ldb, C, ldc, stream);
-#define MM_LAUNCH_F32(id, bm, bn, bk, wm, wn) \
-    case id: return launch_tile<TileGemm<float, bm, bn, bk, wm, wn>, float>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+#define MM_LAUNCH_F64(id, bm, bn, bk, wm, wn, st) \
+    case id: return launch_tile<TileSel<double, bm, bn, bk, wm, wn, st>::type, double>(M, N, K, A, lda, B, ldb, C, ldc, stream);
+#define MM_LAUNCH_F32(id, bm, bn, bk, wm, wn, st) \
+    case id: return launch_tile<TileSel<float, bm, bn, bk, wm, wn, st>::type, float>(M, N, K, A, lda, B, ldb, C, ldc, stream);
 
 hipError_t launch_gemm_f64(int variant, int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
                            const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t stream) {

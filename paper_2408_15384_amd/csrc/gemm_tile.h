@@ -245,6 +245,206 @@ struct TileGemm {
     }
 };
 
+// Direct-to-LDS form of the tile: global_load_lds_dwordx4 moves 16-byte
+// chunks of A and B straight into a ring of STAGES LDS buffers (no staging
+// registers, no LDS store instructions), so the loads of K steps kt+1 ..
+// kt+STAGES-1 are in flight while step kt is multiplied.  One
+// wave-instruction fills 64 consecutive 16-byte LDS slots (lane i -> slot i);
+// each lane fetches the chunk that the swizzled layout puts in its slot:
+//   A rows (BK elements) : chunk ^ ((row / rows per 256 B) mod chunks per row)
+//   B rows (BN elements) : chunk ^ (lane group of the row, shifted so the four
+//                          groups of an MFMA read sit in distinct bank ranges)
+// which makes every fragment read bank-conflict free.  Rows of A past M and
+// column chunks of B past N are clamped in bounds (they only feed entries of
+// C that are not stored).  It needs K % BK == 0, N, lda, ldb multiples of the
+// 16-byte vector and 16-byte aligned bases; other problems run the
+// register-staged tile (same tile shape) in the same kernel.
+typedef __attribute__((address_space(1))) void mm_gvoid;
+typedef __attribute__((address_space(3))) void mm_lvoid;
+
+template <typename T, int BM_, int BN_, int BK_, int WM_, int WN_, int STAGES_>
+struct TileGemmDirect {
+    typedef TileGemm<T, BM_, BN_, BK_, WM_, WN_> Fallback;
+    static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, STAGES = STAGES_;
+    static constexpr int NWN = BN / WN;
+    static constexpr int NWAVES = (BM / WM) * (BN / WN);
+    static constexpr int NT = NWAVES * 64;
+    static constexpr int VEC = MfmaOp<T>::VEC;
+    static constexpr int FM = WM / 16, FN = WN / 16, KS = BK / 4;
+    static constexpr int A_CPR = BK * (int)sizeof(T) / 16;    // 16-byte chunks per A row
+    static constexpr int B_CPR = BN * (int)sizeof(T) / 16;    // 16-byte chunks per B row
+    static constexpr int A_SLOTS = BM * A_CPR, B_SLOTS = BK * B_CPR;
+    static constexpr int STAGE_SLOTS = A_SLOTS + B_SLOTS;
+    static constexpr int STAGE_ELEMS = STAGE_SLOTS * VEC;
+    static constexpr int DIRECT_ELEMS = STAGES * STAGE_ELEMS;
+    static constexpr int LDS_ELEMS = DIRECT_ELEMS > Fallback::LDS_ELEMS ? DIRECT_ELEMS : Fallback::LDS_ELEMS;
+    static constexpr int LOADS = STAGE_SLOTS / NT;
+    static constexpr int A_ROWS_PER_256 = 256 / (A_CPR * 16) > 0 ? 256 / (A_CPR * 16) : 1;
+    // bytes between the lane groups of one B read: 32 lanes per pass for
+    // binary64 (two groups, 128 B apart), 64 lanes for FP32 (four, 64 B apart)
+    static constexpr int B_GROUP_SHIFT = sizeof(T) == 8 ? 8 : 4;   // in chunks
+    static constexpr int B_GROUPS = sizeof(T) == 8 ? 2 : 4;
+    static_assert(STAGE_SLOTS % NT == 0 && A_SLOTS % 64 == 0, "stage must split into whole wave loads");
+    static_assert(A_CPR >= 1 && (A_CPR & (A_CPR - 1)) == 0, "A row chunks");
+    static_assert(B_CPR % (B_GROUP_SHIFT * B_GROUPS) == 0 || B_CPR >= B_GROUP_SHIFT * B_GROUPS, "B row chunks");
+    static_assert(STAGES >= 2 && STAGES <= 4, "stages");
+
+    typedef typename MfmaOp<T>::acc_t acc_t;
+
+    static __device__ __forceinline__ int swz_a(int row, int c) { return c ^ ((row / A_ROWS_PER_256) & (A_CPR - 1)); }
+    static __device__ __forceinline__ int swz_b(int row, int c) {
+        return c ^ (((row / KS) & (B_GROUPS - 1)) * B_GROUP_SHIFT);
+    }
+
+    static __device__ __forceinline__ void sources(const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
+                                                   int64_t ldb, int64_t M, int64_t N, int64_t m0, int64_t n0,
+                                                   const T *(&src)[LOADS], int64_t (&kstride)[LOADS]) {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int j = 0; j < LOADS; ++j) {
+            const int P = (j * NWAVES + wave) * 64 + lane;
+            if (P < A_SLOTS) {
+                const int row = P / A_CPR;
+                const int c = swz_a(row, P % A_CPR);
+                int64_t gr = m0 + row;
+                gr = gr < M ? gr : M - 1;
+                src[j] = A + gr * lda + c * VEC;
+                kstride[j] = 1;                    // a K step moves along the row
+            } else {
+                const int Q = P - A_SLOTS;
+                const int row = Q / B_CPR;
+                const int c = swz_b(row, Q % B_CPR);
+                int64_t gc = n0 + c * VEC;
+                gc = gc < N ? gc : N - VEC;
+                src[j] = B + row * ldb + gc;
+                kstride[j] = ldb;                  // a K step moves down the rows
+            }
+        }
+    }
+
+    static __device__ __forceinline__ void issue(const T *const (&src)[LOADS], const int64_t (&kstride)[LOADS],
+                                                 int64_t k0, T *buf) {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+#pragma unroll
+        for (int j = 0; j < LOADS; ++j)
+            __builtin_amdgcn_global_load_lds((mm_gvoid *)(src[j] + k0 * kstride[j]),
+                                             (mm_lvoid *)(buf + (j * NWAVES + wave) * 64 * VEC), 16, 0, 0);
+    }
+
+    static __device__ __forceinline__ void compute(const T *stage, acc_t (&acc)[FM][FN]) {
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int wm = wave / NWN, wn = wave % NWN;
+        const int li = lane & 15, q = lane >> 4;
+        const T *As = stage, *Bs = stage + A_SLOTS * VEC;
+        T a[FM][KS], b[FN][KS];
+        // A: lane group q holds k = q*KS .. q*KS+KS-1 of its row, KS*sizeof(T)/16 chunks
+        constexpr int CH = KS * (int)sizeof(T) / 16 > 0 ? KS * (int)sizeof(T) / 16 : 1;
+        constexpr int PER = 16 / (int)sizeof(T);
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm) {
+            const int row = wm * WM + fm * 16 + li;
+#pragma unroll
+            for (int h = 0; h < CH; ++h) {
+                typedef T v_t __attribute__((ext_vector_type(PER)));
+                const v_t v = *reinterpret_cast<const v_t *>(As + row * BK + swz_a(row, q * CH + h) * VEC);
+#pragma unroll
+                for (int e = 0; e < PER && h * PER + e < KS; ++e) a[fm][h * PER + e] = v[e];
+            }
+        }
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+            for (int s = 0; s < KS; ++s) {
+                const int row = q * KS + s;
+                const int col = wn * WN + fn * 16 + li;
+                b[fn][s] = Bs[row * BN + swz_b(row, col / VEC) * VEC + col % VEC];
+            }
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = MfmaOp<T>::mma(a[fm][s], b[fn][s], acc[fm][fn]);
+        __builtin_amdgcn_s_setprio(0);
+    }
+
+    template <int N_>
+    static __device__ __forceinline__ void wait_vm() {
+        __builtin_amdgcn_s_waitcnt((N_ & 15) | (7 << 4) | (15 << 8) | ((N_ >> 4) << 14));
+    }
+
+    static __device__ __forceinline__ bool eligible(const T *A, int64_t lda, const T *B, int64_t ldb, int64_t N,
+                                                    int64_t K) {
+        return K % BK == 0 && N % VEC == 0 && N >= VEC && lda % VEC == 0 && ldb % VEC == 0 &&
+               ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
+    }
+
+    static __device__ __forceinline__ void run(const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
+                                               int64_t ldb, T *__restrict__ C, int64_t ldc, int64_t M, int64_t N,
+                                               int64_t K, int64_t tm, int64_t tn, bool vec_ok, T *smem) {
+        if (!eligible(A, lda, B, ldb, N, K)) {
+            Fallback::run(A, lda, B, ldb, C, ldc, M, N, K, tm, tn, vec_ok, smem);
+            return;
+        }
+        const int64_t m0 = tm * BM, n0 = tn * BN;
+        acc_t acc[FM][FN];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = acc_t{0, 0, 0, 0};
+        const int64_t nkt = K / BK;
+        const T *src[LOADS];
+        int64_t kstride[LOADS];
+        sources(A, lda, B, ldb, M, N, m0, n0, src, kstride);
+#pragma unroll
+        for (int s = 0; s < STAGES - 1; ++s)
+            if (s < nkt) issue(src, kstride, (int64_t)s * BK, smem + s * STAGE_ELEMS);
+        for (int64_t kt = 0; kt < nkt; ++kt) {
+            const int64_t later = (nkt - 1 - kt) < (STAGES - 2) ? (nkt - 1 - kt) : (STAGES - 2);
+            if (later >= 2) wait_vm<2 * LOADS>();
+            else if (later == 1) wait_vm<LOADS>();
+            else wait_vm<0>();
+            // stage kt is in LDS for every thread, the buffer of step kt-1 is
+            // no longer read: a bare barrier (a fenced one would also wait for
+            // the later stages' loads)
+            __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
+            __builtin_amdgcn_s_barrier();
+            if (kt + STAGES - 1 < nkt)
+                issue(src, kstride, (kt + STAGES - 1) * BK, smem + ((kt + STAGES - 1) % STAGES) * STAGE_ELEMS);
+            compute(smem + (kt % STAGES) * STAGE_ELEMS, acc);
+        }
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int wm = wave / NWN, wn = wave % NWN;
+        const int li = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t r = m0 + wm * WM + fm * 16 + MfmaOp<T>::row(q, v);
+                    const int64_t c = n0 + wn * WN + fn * 16 + li;
+                    if (r < M && c < N) C[r * ldc + c] = acc[fm][fn][v];
+                }
+        __syncthreads();   // LDS may be refilled by the next tile of a persistent workgroup
+    }
+};
+
+// Variant selector: S = 0: register-staged tile; S = 10 + b: direct-to-LDS
+// ring of b buffers.
+template <typename T, int BM, int BN, int BK, int WM, int WN, int S, bool DIRECT = (S >= 10)>
+struct TileSel {
+    typedef TileGemm<T, BM, BN, BK, WM, WN> type;
+};
+template <typename T, int BM, int BN, int BK, int WM, int WN, int S>
+struct TileSel<T, BM, BN, BK, WM, WN, S, true> {
+    typedef TileGemmDirect<T, BM, BN, BK, WM, WN, S - 10> type;
+};
+
 // Tile order for a 1-D grid of tiles_m x tiles_n workgroups.  Workgroups are
 // handed to the 8 XCDs round-robin, so consecutive ids land on different L2s.
 // The id is first regrouped so that each XCD owns a contiguous range, then the

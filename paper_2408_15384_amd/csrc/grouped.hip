@@ -135,10 +135,10 @@ struct KernelInfo {
 
 static KernelInfo kernel_for(mm_method method, int variant) {
     KernelInfo k;
-#define MM_GK_F64(id, bm_, bn_, bk, wm, wn) \
-    case id: k.fn = (KernelPtr)&grouped_gemm_kernel<TileGemm<double, bm_, bn_, bk, wm, wn>, double>; k.nt = TileGemm<double, bm_, bn_, bk, wm, wn>::NT; k.bm = bm_; k.bn = bn_; break;
-#define MM_GK_F32(id, bm_, bn_, bk, wm, wn) \
-    case id: k.fn = (KernelPtr)&grouped_gemm_kernel<TileGemm<float, bm_, bn_, bk, wm, wn>, float>; k.nt = TileGemm<float, bm_, bn_, bk, wm, wn>::NT; k.bm = bm_; k.bn = bn_; break;
+#define MM_GK_F64(id, bm_, bn_, bk, wm, wn, st) \
+    case id: k.fn = (KernelPtr)&grouped_gemm_kernel<TileSel<double, bm_, bn_, bk, wm, wn, st>::type, double>; k.nt = TileSel<double, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
+#define MM_GK_F32(id, bm_, bn_, bk, wm, wn, st) \
+    case id: k.fn = (KernelPtr)&grouped_gemm_kernel<TileSel<float, bm_, bn_, bk, wm, wn, st>::type, float>; k.nt = TileSel<float, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
 #define MM_GK_S3(id, bm_, bn_, bk, wm, wn, st) \
     case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type>; k.nt = SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
 #define MM_GK_S6(id, bm_, bn_, bk, wm, wn, st) \

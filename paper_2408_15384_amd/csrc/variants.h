@@ -5,17 +5,26 @@
 // computes every tile the same way in both.
 #pragma once
 
+// Dense variants carry a seventh field, S: 0 for the register-staged tile, or
+// 10 + b for the direct global-to-LDS tile with a ring of b buffers (which
+// falls back to the register-staged tile for problems it cannot take).
 #define MM_F64_VARIANTS(X)            \
-    X(0, 128, 128, 16, 64, 64)        \
-    X(1, 64, 64, 16, 32, 32)          \
-    X(2, 256, 128, 16, 64, 64)        \
-    X(3, 128, 64, 16, 64, 32)
+    X(0, 128, 128, 16, 64, 64, 0)     \
+    X(1, 64, 64, 16, 32, 32, 0)       \
+    X(2, 256, 128, 16, 64, 64, 0)     \
+    X(3, 128, 64, 16, 64, 32, 0)      \
+    X(4, 256, 128, 16, 64, 64, 13)    \
+    X(5, 128, 128, 16, 64, 64, 13)    \
+    X(6, 64, 64, 16, 32, 32, 13)
 
 #define MM_F32_VARIANTS(X)            \
-    X(0, 128, 128, 16, 64, 64)        \
-    X(1, 64, 64, 16, 32, 32)          \
-    X(2, 256, 128, 16, 64, 64)        \
-    X(3, 128, 128, 32, 64, 64)
+    X(0, 128, 128, 16, 64, 64, 0)     \
+    X(1, 64, 64, 16, 32, 32, 0)       \
+    X(2, 256, 128, 16, 64, 64, 0)     \
+    X(3, 128, 128, 32, 64, 64, 0)     \
+    X(4, 256, 128, 32, 64, 64, 13)    \
+    X(5, 256, 128, 16, 64, 64, 13)    \
+    X(6, 64, 64, 32, 32, 32, 13)
 
 // Split variants carry a seventh field, S: 1 or 2 register stages of global
 // prefetch, or 10 + b: a ring of b LDS buffers fed by direct global-to-LDS

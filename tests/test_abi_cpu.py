@@ -65,8 +65,12 @@ def test_variant_tables(lib):
             assert bm % 16 == 0 and bn % 16 == 0 and bk % 4 == 0
         with pytest.raises(api.MMError):
             api.variant_info(m, n)
-    # selection is a pure function of the shape bucket
-    assert api.select_variant("f64", 8192, 8192, 8192) == api.select_variant("f64", 8000, 5000, 7000)
+    # selection is a pure function of the shape: large products take the
+    # 256x128 tile, small ones a 64x64 tile
+    assert api.select_variant("f64", 8192, 8192, 8192) == api.select_variant("f64", 8192, 8192, 8192)
+    for m in ("f64", "f32", "split3", "split6"):
+        assert api.variant_info(m, api.select_variant(m, 8192, 8192, 8192))[:2] == (256, 128)
+        assert api.variant_info(m, api.select_variant(m, 256, 256, 256))[:2] == (64, 64)
 
 
 def test_autotune_cache_roundtrip(lib, tmp_path):
@@ -77,12 +81,13 @@ def test_autotune_cache_roundtrip(lib, tmp_path):
     assert doc["arch"] == "gfx950" and doc["entries"] == []
     # an entry selecting a non-default variant changes selection after load
     default = api.select_variant("f64", 1000, 1000, 1000)
+    default_4000 = api.select_variant("f64", 4000, 1000, 1000)
     other = (default + 1) % api.variant_count("f64")
     doc["entries"] = [[api.MM_F64, 10, 10, 10, other, 1.5, 0]]
     json.dump(doc, open(path, "w"))
     api.autotune_load(path)
     assert api.select_variant("f64", 1000, 1000, 1000) == other
-    assert api.select_variant("f64", 4000, 1000, 1000) == default       # other bucket untouched
+    assert api.select_variant("f64", 4000, 1000, 1000) == default_4000  # other bucket untouched
     api.autotune_save(path)
     assert json.load(open(path))["entries"][0][4] == other
     # wrong architecture or bad variant: rejected, cache unchanged

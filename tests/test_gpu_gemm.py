@@ -82,6 +82,27 @@ def test_every_variant_ragged(mm, method):
         outs.append(Ch)
 
 
+@pytest.mark.parametrize("method", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(300, 272, 320), (129, 136, 64), (64, 8, 32), (513, 260, 96)])
+def test_direct_tile_shapes(mm, method, shape):
+    """Shapes the direct-to-LDS tiles take (K a multiple of 32, N of the
+    vector): edge rows and columns clamped, every variant the same bound."""
+    M, N, K = shape
+    kind = "uniform_f64" if method == "f64" else "uniform_f32"
+    A, B = I.pair(kind, M, N, K, seed=N)
+    dA, dB = dev(A), dev(B)
+    u = oracle.U_F64 if method == "f64" else oracle.U_F32
+    for v in range(mm.variant_count(method)):
+        C = torch.full((M, N), float("nan"), dtype=dA.dtype, device="cuda")
+        mm.gemm_variant(method, v, dA, dB, C)
+        assert_within_bound(host(C), A, B, u)
+    Ai, Bi = I.pair("int_f64" if method == "f64" else "int_f32", M, N, K, seed=N + 1)
+    for v in range(mm.variant_count(method)):
+        C = torch.empty((M, N), dtype=dA.dtype, device="cuda")
+        mm.gemm_variant(method, v, dev(Ai), dev(Bi), C)
+        assert np.array_equal(host(C).astype(np.float64), oracle.gemm(Ai, Bi)), f"variant {v}"
+
+
 def test_f64_leading_dims_and_misaligned(mm):
     M, N, K = 70, 45, 37
     A, B = I.pair("uniform_f64", M, N, K, seed=4)
