@@ -21,7 +21,14 @@ Also reported in the same line (context, not the headline):
     [64, 4096], half binary64, half FP32-accurate split), operands resident on
     the device, a 64 GiB admission budget; p50/p99 latency and throughput.
 
-Usage: python bench.py [--gpus 1] [--steps 15] [--warmup 3] [--sections precision,grouped,serving|none]
+  * strassen: one Strassen-Winograd level on the binary64 product at 8192;
+  * shard: one GPU's share (1024 rows) of a row-sharded 8192 product;
+  * layouts: transposed operands (NN, NT, TN, TT) at 8192;
+  * paper sizes: the paper's experiment (Box-Muller inputs, 32..1024), GPU
+    against the oracle on one and on all host cores.
+
+Usage: python bench.py [--gpus 1] [--steps 15] [--warmup 3]
+                       [--sections precision,grouped,serving,strassen,shard,layouts,paper|none]
                        [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -59,9 +66,10 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(n_launch_bytes):
+def read_traffic(variant):
     """HBM bytes per launch of the headline kernel from the committed rocprofv3
-    counter summary, or None when it is missing or was taken on other sources."""
+    counter summary, or None when it is missing, was taken on other sources or
+    on another tile variant."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -70,6 +78,8 @@ def read_traffic(n_launch_bytes):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
     if vals.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    if vals.get("tile_variant") != str(variant):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -316,6 +326,18 @@ def serving_section(torch, mm, wl=None, slots=4, max_batch=64, budget=64 << 30, 
             R = oracle.split_product(A, B, 6)
             bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F32) + 2.0 ** -24 * np.abs(R)
         worst = max(worst, float((np.abs(got - R) / np.maximum(bound, 1e-300)).max()))
+    # binary64 residual probe (Freivalds) of every served result, on the GPU
+    res2 = torch.empty((count, 2), dtype=torch.float64, device="cuda")
+    x_all = torch.from_numpy(I.probe_vector(4096)).cuda()
+    rws = torch.empty(mm.lib().mm_residual_workspace_bytes(4096, 4096, 4096), dtype=torch.uint8, device="cuda")
+    for i, (prob, method, _, C, A, B) in enumerate(wl.reqs):
+        mm.residual_f64(A, B, C, x_all[:prob.N], out=res2[i], workspace=rws)
+    r2z2 = res2.cpu().numpy()
+    rel = np.sqrt(r2z2[:, 0] / np.maximum(r2z2[:, 1], 1e-300))
+    f64_mask = np.array([m == mm.MM_F64 for _, m, *_ in wl.reqs])
+    freivalds = {k: {"requests": int(msk.sum()), "median": float(np.median(rel[msk])), "max": float(rel[msk].max())}
+                 for k, msk in (("f64", f64_mask), ("split6", ~f64_mask)) if msk.any()}
+    del res2, rws
     flop = float(sum(2.0 * d[0] * d[1] * d[2] for d in wl.dims))
     span = float(wl.t_arr[-1])
     mix_roof_s = sum(2.0 * d[0] * d[1] * d[2] / (PEAK["f64"] * 1e12) if f else
@@ -327,7 +349,8 @@ def serving_section(torch, mm, wl=None, slots=4, max_batch=64, budget=64 << 30, 
            "max_ms": stats["max_ms"], "tflops": stats["tflops"], "useful_flop": flop,
            "offered_load_rho": mix_roof_s / span, "peak_bytes_in_flight": stats["peak_bytes"],
            "launches": stats["launches"], "mean_batch": stats["mean_batch"],
-           "oracle_checked": len(sample), "oracle_max_err_over_bound": worst}
+           "oracle_checked": len(sample), "oracle_max_err_over_bound": worst,
+           "freivalds_rel_residual_all": freivalds}
     log(f"  serving slots={slots} batch={max_batch} v={variants}: p50 {res['p50_ms']:.3f} ms "
         f"p99 {res['p99_ms']:.3f} ms {res['tflops']:.1f} TFLOP/s, {res['launches']} launches")
     return res
@@ -349,6 +372,31 @@ def strassen_section(torch, mm, n=8192, reps=5):
            "normwise_err_vs_oracle_rows0_7": float(np.linalg.norm(Ch - R) / np.linalg.norm(R))}
     log(f"  strassen: {ev:.3f} ms {out['tflops_equiv']:.2f} TFLOP/s-equivalent err {out['normwise_err_vs_oracle_rows0_7']:.2e}")
     del dA, dB, C, ws
+    torch.cuda.empty_cache()
+    return out
+
+
+def shard_section(torch, mm, n=8192, parts=8, reps=15):
+    """One GPU's share of a row-sharded binary64 product at n: A's and C's rows
+    [0, n/parts) times all of B.  Rows of C do not depend on how the rows are
+    split, so the share must equal the same rows of the whole product bit for
+    bit when both run the same tile variant."""
+    m = n // parts
+    A, B = I.pair("uniform_f64", n, n, n, seed=0)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    del A, B
+    Cs = torch.empty((m, n), dtype=torch.float64, device="cuda")
+    v = mm.select_variant("f64", m, n, n)
+    wall, ev, med, mn = timed_steps(torch, lambda: mm.gemm_variant("f64", v, dA[:m], dB, Cs), reps, 3)
+    Cf = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    mm.gemm_variant("f64", v, dA, dB, Cf)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(Cs, Cf[:m]))
+    out = {"M": m, "N": n, "K": n, "of_parts": parts, "tile_variant": v, "ms": ev, "ms_median": med,
+           "tflops": 2.0 * m * n * n / (ev * 1e-3) / 1e12, "rows_equal_whole_product": same,
+           "note": "compute of one GPU's share only; the all-gather of B is not part of this figure"}
+    log(f"  shard {m}x{n}x{n}: {ev:.3f} ms {out['tflops']:.2f} TFLOP/s, rows equal: {same}")
+    del dA, dB, Cs, Cf
     torch.cuda.empty_cache()
     return out
 
@@ -426,8 +474,8 @@ def main():
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--sections", default="precision,grouped,serving,strassen,layouts,paper",
-                    help="comma list of sections to run after the headline (precision, grouped, serving, strassen, layouts, "
+    ap.add_argument("--sections", default="precision,grouped,serving,strassen,shard,layouts,paper",
+                    help="comma list of sections to run after the headline (precision, grouped, serving, strassen, shard, layouts, "
                          "paper; "
                          "or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -457,8 +505,8 @@ def main():
     flop = 2.0 * n ** 3
     value = flop / (wall_ms * 1e-3) / 1e12
     achieved = flop / (ev_ms * 1e-3) / 1e12
-    traffic = read_traffic(24.0 * n * n)
     variant = mm.select_variant("f64", n, n, n)
+    traffic = read_traffic(variant) if n == 8192 else None
     C = dC.cpu().numpy()
     x = torch.from_numpy(I.probe_vector(n)).cuda()
     r2z2 = mm.residual_f64(dA, dB, dC, x).cpu().numpy()
@@ -497,6 +545,9 @@ def main():
     if "strassen" in sections:
         log("strassen: one Strassen-Winograd level at N=8192")
         line["strassen"] = strassen_section(torch, mm)
+    if "shard" in sections:
+        log("shard: one GPU's share of a row-sharded product at N=8192")
+        line["shard"] = shard_section(torch, mm)
     if "layouts" in sections:
         log("layouts: transposed operands at N=8192")
         line["layouts"] = layouts_section(torch, mm)

@@ -78,3 +78,35 @@ def test_column_major_product(mm):
     torch.cuda.synchronize()
     C = C_cm.cpu().numpy().reshape(N, M).T      # column-major buffer read back
     assert np.array_equal(C, oracle.gemm(A, B))
+
+
+# ------------------------------------------------------------ command line
+
+@pytest.mark.parametrize("argv", [
+    ["96", "80", "72"],
+    ["64", "48", "80", "--method", "split6", "--inputs", "normal", "--trans-b"],
+    ["64", "48", "80", "--method", "f32", "--trans-a", "--trans-b"],
+    ["96", "64", "128", "--method", "strassen", "--inputs", "int"],
+])
+def test_cli_runs_on_gpu(argv):
+    from paper_2408_15384_amd import cli
+    a = cli.parse(argv + ["--reps", "3", "--warmup", "1"])
+    res = cli.run(a)
+    assert res["median_s"] > 0 and res["min_s"] <= res["median_s"]
+    tol = 1e-5 if a.method in ("f32", "split6") else 1e-13
+    assert res["freivalds_rel_residual"] < tol
+
+
+def test_row_shard_equals_rows_of_whole_product(mm):
+    # one GPU's share of a row-sharded product: the same rows, bit for bit
+    n, m = 1536, 192
+    A, B = I.pair("uniform_f64", n, n, n, seed=31)
+    dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+    for v in range(mm.variant_count("f64")):
+        Cf = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        mm.gemm_variant("f64", v, dA, dB, Cf)
+        for r0 in (0, 5 * m):
+            Cs = torch.empty((m, n), dtype=torch.float64, device="cuda")
+            mm.gemm_variant("f64", v, dA[r0:r0 + m], dB, Cs)
+            torch.cuda.synchronize()
+            assert torch.equal(Cs, Cf[r0:r0 + m]), f"variant {v} rows {r0}.."
