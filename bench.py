@@ -50,7 +50,7 @@ from paper_2408_15384_amd import inputs as I  # noqa: E402
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}   # dense TFLOP/s, MI355X datasheet
 HBM_TBS = 8.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_f64_8192.txt")
-KERNEL_SOURCES = ["paper_2408_15384_amd/csrc/gemm_tile.h", "paper_2408_15384_amd/csrc/gemm_mfma.hip",
+KERNEL_SOURCES = ["paper_2408_15384_amd/csrc/gemm_tile.h", "paper_2408_15384_amd/csrc/gptr.h", "paper_2408_15384_amd/csrc/gemm_mfma.hip",
                   "paper_2408_15384_amd/csrc/variants.h"]
 
 

@@ -112,7 +112,9 @@ mm_status mm_split_bf16(int64_t rows, int64_t cols, const float *X, int64_t ldx,
                         int32_t nplanes, int32_t transpose,
                         uint16_t *planes, int64_t plane_stride, void *stream);
 
-/* Bytes of device workspace mm_gemm_split_bf16 needs for this shape. */
+/* Bytes of device workspace mm_gemm_split_bf16 may need for this shape (the
+ * planes of both operands): an upper bound, since the fused tile variants
+ * split inside the product and use none. */
 size_t mm_split_workspace_bytes(int64_t M, int64_t N, int64_t K, int32_t nprod);
 
 /*
@@ -123,10 +125,14 @@ size_t mm_split_workspace_bytes(int64_t M, int64_t N, int64_t K, int32_t nprod);
  *   nprod = 6: h.h + h.m + m.h + h.l + m.m + l.h
  * are accumulated in FP32 in two accumulator sets (the leading h.h product and
  * the sum of the corrections), and each entry is recombined in binary64 as
- * (double)lead + (double)corr before being stored.
+ * (double)lead + (double)corr before being stored.  Depending on the tile
+ * variant the planes are made by a split pass into the workspace or by the
+ * product tile itself on the way into on-chip memory ("fused" variants); the
+ * planes, and hence the result, are the same bits either way.
  *   C         : device; FP32 (c_is_f64 == 0) or binary64 (c_is_f64 != 0), ldc in elements
  *   workspace : device scratch of at least mm_split_workspace_bytes(M,N,K,nprod)
  *               bytes, or NULL to let the library allocate it stream-ordered
+ *               when the chosen variant needs it
  * Design error against the exact product: about 4e-6 normwise for nprod = 3 on
  * zero-mean data, below 1e-6 for nprod = 6.  nprod not in {3, 6} is MM_E_INVAL.
  */
@@ -328,7 +334,7 @@ mm_status mm_autotune_clear(void);
 typedef struct mm_server mm_server;
 
 typedef struct mm_serve_config {
-    uint64_t budget_bytes;   /* admission budget: bytes of operands, results and workspace in flight */
+    uint64_t budget_bytes;   /* admission budget: bytes of operands, results and split planes in flight */
     int32_t slots;           /* concurrent launch slots (one HIP stream each), 1..8 */
     int32_t max_batch;       /* most requests packed into one grouped launch, 1..4096 */
     int32_t queue_capacity;  /* most requests waiting for admission; submit beyond it is MM_E_BUSY */

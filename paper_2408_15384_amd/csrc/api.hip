@@ -204,13 +204,14 @@ static mm_status run_split(int variant, int64_t M, int64_t N, int64_t K, const f
         MM_HIP(launch_fill_zero(C, M, N, ldc, c_is_f64 ? 8 : 4, st));
         return MM_OK;
     }
-    const size_t need = split_workspace_bytes(M, N, K, nprod);
+    // fused variants split inside the product and need no plane workspace
+    const size_t need = split_variant_fused(variant) ? 0 : split_workspace_bytes(M, N, K, nprod);
     void *ws = workspace;
     bool owned = false;
-    if (!ws) {
+    if (need && !ws) {
         MM_HIP(hipMallocAsync(&ws, need, st));
         owned = true;
-    } else if (workspace_bytes < need) {
+    } else if (need && workspace_bytes < need) {
         return fail(MM_E_INVAL, "workspace too small");
     }
     hipError_t e = launch_split_product(variant, nprod, 0, 0, M, N, K, A, lda, B, ldb, C, ldc, c_is_f64, ws, st);

@@ -51,28 +51,37 @@ Key key_of(mm_method m, int64_t M, int64_t N, int64_t K) {
 // sustains on a large product (measured on MI355X, in TFLOP/s of 2MNK).  The
 // model picks the candidate whose busiest unit finishes first; it charges
 // the padding of ragged edge tiles and the idle units of a small grid, which
-// is what decides between tile sizes.
+// is what decides between tile sizes.  Split variants that read planes are
+// also charged their plane pass: the FP32 operands read once and the planes
+// written once at 4 TB/s, plus 6 us for its two launches; fused split
+// variants have no pass.
 struct Candidate {
     int variant;
     int bm, bn;
     double rate;
+    bool plane_pass;
 };
 
-const Candidate kF64Cand[] = {{4, 256, 128, 65.4}, {3, 128, 64, 56.3}, {6, 64, 64, 60.8}};
-const Candidate kF32Cand[] = {{2, 256, 128, 132.2}, {3, 128, 128, 122.4}, {6, 64, 64, 107.4}};
-const Candidate kSplit3Cand[] = {{9, 256, 128, 330.0}, {6, 128, 128, 277.0}, {8, 64, 64, 217.0}};
-const Candidate kSplit6Cand[] = {{9, 256, 128, 203.7}, {6, 128, 128, 182.9}, {8, 64, 64, 120.9}};
+const Candidate kF64Cand[] = {{4, 256, 128, 65.4, false}, {3, 128, 64, 56.3, false}, {6, 64, 64, 60.8, false}};
+const Candidate kF32Cand[] = {{2, 256, 128, 132.2, false}, {3, 128, 128, 122.4, false}, {6, 64, 64, 107.4, false}};
+const Candidate kSplit3Unfused[] = {{9, 256, 128, 330.0, true}, {6, 128, 128, 277.0, true}, {8, 64, 64, 217.0, true}};
+const Candidate kSplit6Unfused[] = {{9, 256, 128, 203.7, true}, {6, 128, 128, 182.9, true}, {8, 64, 64, 120.9, true}};
+const Candidate kSplit3Cand[] = {{9, 256, 128, 330.0, true},  {6, 128, 128, 277.0, true},  {8, 64, 64, 217.0, true},
+                                 {10, 64, 64, 193.6, false},  {11, 128, 64, 234.7, false}, {12, 128, 128, 202.1, false}};
+const Candidate kSplit6Cand[] = {{9, 256, 128, 203.7, true},  {6, 128, 128, 182.9, true},  {8, 64, 64, 120.9, true},
+                                 {10, 64, 64, 127.8, false},  {11, 128, 64, 147.1, false}, {12, 128, 128, 153.3, false}};
 
 constexpr double kCUs = 256.0;
 
-template <size_t N>
-int pick(const Candidate (&c)[N], int64_t M, int64_t N_, int64_t K) {
+template <size_t NC>
+int pick(const Candidate (&c)[NC], int64_t M, int64_t N, int64_t K, int planes) {
     int best = c[0].variant;
     double best_t = 0;
-    for (size_t i = 0; i < N; ++i) {
-        const double tiles = (double)((M + c[i].bm - 1) / c[i].bm) * (double)((N_ + c[i].bn - 1) / c[i].bn);
-        const double per_cu = std::ceil(tiles / kCUs);
-        const double t = per_cu * 2.0 * c[i].bm * c[i].bn * (double)std::max<int64_t>(K, 1) * kCUs / c[i].rate;
+    const double k = (double)std::max<int64_t>(K, 1);
+    for (size_t i = 0; i < NC; ++i) {
+        const double tiles = (double)((M + c[i].bm - 1) / c[i].bm) * (double)((N + c[i].bn - 1) / c[i].bn);
+        double t = std::ceil(tiles / kCUs) * 2.0 * c[i].bm * c[i].bn * k * kCUs / (c[i].rate * 1e12);
+        if (c[i].plane_pass) t += ((double)M * k + k * (double)N) * (4.0 + 2.0 * planes) / 4e12 + 6e-6;
         if (i == 0 || t < best_t) {
             best = c[i].variant;
             best_t = t;
@@ -81,13 +90,22 @@ int pick(const Candidate (&c)[N], int64_t M, int64_t N_, int64_t K) {
     return best;
 }
 
+}  // namespace
+
+int default_unfused_split_variant(mm_method method, int64_t M, int64_t N, int64_t K) {
+    if (M <= 0 || N <= 0) return 1;
+    return method == MM_SPLIT_BF16_3 ? pick(kSplit3Unfused, M, N, K, 2) : pick(kSplit6Unfused, M, N, K, 3);
+}
+
+namespace {
+
 int default_variant(mm_method method, int64_t M, int64_t N, int64_t K) {
     if (M <= 0 || N <= 0) return 1;
     switch (method) {
-        case MM_F64: return pick(kF64Cand, M, N, K);
-        case MM_F32: return pick(kF32Cand, M, N, K);
-        case MM_SPLIT_BF16_3: return pick(kSplit3Cand, M, N, K);
-        case MM_SPLIT_BF16_6: return pick(kSplit6Cand, M, N, K);
+        case MM_F64: return pick(kF64Cand, M, N, K, 0);
+        case MM_F32: return pick(kF32Cand, M, N, K, 0);
+        case MM_SPLIT_BF16_3: return pick(kSplit3Cand, M, N, K, 2);
+        case MM_SPLIT_BF16_6: return pick(kSplit6Cand, M, N, K, 3);
     }
     return 0;
 }

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gptr.h"
+
 namespace mm {
 
 template <typename T> struct MfmaOp;
@@ -83,7 +85,7 @@ struct TileGemm {
 
     // Global -> registers for the slice starting at k0.  Out-of-range elements
     // (beyond M, N or K) read as zero so ragged edges add nothing.
-    static __device__ __forceinline__ void load_a(vec_t (&ra)[A_VECS], const T *__restrict__ A, int64_t lda,
+    static __device__ __forceinline__ void load_a(vec_t (&ra)[A_VECS], gptr<const T> A, int64_t lda,
                                                   int rows_left, int64_t K, int64_t k0, bool vec_ok) {
         const int tid = threadIdx.x;
         const bool kfull = vec_ok && (k0 + BK <= K);
@@ -92,9 +94,9 @@ struct TileGemm {
             const int v = tid + i * NT;
             const int r = v / AV_ROW;
             const int c = (v % AV_ROW) * VEC;
-            const T *p = A + (int64_t)r * lda + k0 + c;
+            gptr<const T> p = A + (int64_t)r * lda + k0 + c;
             if (r < rows_left && kfull) {
-                ra[i] = *reinterpret_cast<const vec_t *>(p);
+                ra[i] = *reinterpret_cast<gptr<const vec_t>>(p);
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
@@ -103,7 +105,7 @@ struct TileGemm {
         }
     }
 
-    static __device__ __forceinline__ void load_b(vec_t (&rb)[B_VECS], const T *__restrict__ B, int64_t ldb,
+    static __device__ __forceinline__ void load_b(vec_t (&rb)[B_VECS], gptr<const T> B, int64_t ldb,
                                                   int cols_left, int64_t K, int64_t k0, bool vec_ok) {
         const int tid = threadIdx.x;
 #pragma unroll
@@ -111,10 +113,10 @@ struct TileGemm {
             const int v = tid + i * NT;
             const int r = v / BV_ROW;
             const int c = (v % BV_ROW) * VEC;
-            const T *p = B + (k0 + r) * ldb + c;
+            gptr<const T> p = B + (k0 + r) * ldb + c;
             const bool krow = (k0 + r < K);
             if (krow && vec_ok && c + VEC <= cols_left) {
-                rb[i] = *reinterpret_cast<const vec_t *>(p);
+                rb[i] = *reinterpret_cast<gptr<const vec_t>>(p);
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
@@ -182,8 +184,9 @@ struct TileGemm {
         const int64_t m0 = tm * BM, n0 = tn * BN;
         const int rows_left = (int)((M - m0) < BM ? (M - m0) : BM);
         const int cols_left = (int)((N - n0) < BN ? (N - n0) : BN);
-        const T *Ab = A + m0 * lda;
-        const T *Bb = B + n0;
+        const gptr<const T> Ab = (gptr<const T>)A + m0 * lda;
+        const gptr<const T> Bb = (gptr<const T>)B + n0;
+        const gptr<T> Cg = (gptr<T>)C;
 
         acc_t acc[FM][FN];
 #pragma unroll
@@ -240,7 +243,7 @@ struct TileGemm {
                 for (int v = 0; v < 4; ++v) {
                     const int r = wm * WM + fm * 16 + MfmaOp<T>::row(q, v);
                     const int c = wn * WN + fn * 16 + li;
-                    if (r < rows_left && c < cols_left) C[(m0 + r) * ldc + n0 + c] = acc[fm][fn][v];
+                    if (r < rows_left && c < cols_left) Cg[(m0 + r) * ldc + n0 + c] = acc[fm][fn][v];
                 }
     }
 };
@@ -428,7 +431,7 @@ struct TileGemmDirect {
                 for (int v = 0; v < 4; ++v) {
                     const int64_t r = m0 + wm * WM + fm * 16 + MfmaOp<T>::row(q, v);
                     const int64_t c = n0 + wn * WN + fn * 16 + li;
-                    if (r < M && c < N) C[r * ldc + c] = acc[fm][fn][v];
+                    if (r < M && c < N) ((gptr<T>)C)[r * ldc + c] = acc[fm][fn][v];
                 }
         __syncthreads();   // LDS may be refilled by the next tile of a persistent workgroup
     }

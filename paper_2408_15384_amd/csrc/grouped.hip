@@ -31,38 +31,80 @@ namespace mm {
 
 // ------------------------------------------------------------------ device side
 
-__device__ __forceinline__ int find_owner(const GroupedDesc *__restrict__ descs, int count, int64_t t) {
+// The owner search reads the prefix sums from LDS when they fit (CAP entries,
+// tile ids below 2^31): one pass of global loads per workgroup instead of a
+// chain of dependent global loads per tile.
+template <int CAP, typename D>
+__device__ __forceinline__ bool stage_begins(const D *__restrict__ descs, int count, int64_t total_tiles,
+                                             int32_t *s_begin) {
+    const bool cached = count <= CAP && total_tiles <= (int64_t)0x7fffffff;
+    if (cached) {
+        for (int i = threadIdx.x; i < count; i += blockDim.x) s_begin[i] = (int32_t)descs[i].tile_begin;
+        __syncthreads();
+    }
+    return cached;
+}
+
+template <typename D>
+__device__ __forceinline__ int find_owner(const D *__restrict__ descs, const int32_t *s_begin, bool cached, int count,
+                                          int64_t t) {
     int lo = 0, hi = count - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (descs[mid].tile_begin <= t) lo = mid;
+        const int64_t b = cached ? (int64_t)s_begin[mid] : descs[mid].tile_begin;
+        if (b <= t) lo = mid;
         else hi = mid - 1;
     }
     return lo;
 }
 
-// Next tile id: fixed stride, or the shared work counter.
-__device__ __forceinline__ int64_t next_tile(int64_t cur, int *counter, int64_t *slot) {
+// Tile ids and owner indices are the same in every lane; reading them from
+// the first lane makes that visible to the compiler, so the descriptor is
+// fetched with scalar loads into scalar registers rather than occupying
+// vector registers next to the accumulators.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ int64_t uniform(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+constexpr int kOwnerCap = 1024;     // problems whose prefix sums are staged in LDS
+constexpr int kJobCap = 2048;       // split jobs likewise
+
+// Work counter: thread 0 draws the ticket of the workgroup's next tile when a
+// tile starts (its latency hides behind the tile's loads); after the tile the
+// ticket is broadcast through LDS.  Ticket j names tile gridDim.x + j, since
+// the first gridDim.x tiles are taken by blockIdx.
+__device__ __forceinline__ int draw_ticket(int *counter) {
+    return (counter && threadIdx.x == 0) ? atomicAdd(counter, 1) : 0;
+}
+
+__device__ __forceinline__ int64_t next_tile(int64_t cur, const int *counter, int ticket, int64_t *slot) {
     if (!counter) return cur + gridDim.x;
+    if (threadIdx.x == 0) *slot = (int64_t)ticket + gridDim.x;
     __syncthreads();
-    if (threadIdx.x == 0) *slot = (int64_t)atomicAdd(counter, 1) + gridDim.x;
-    __syncthreads();
-    return *slot;
+    return uniform(*slot);
 }
 
 template <typename TG, typename T>
 __global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 ? 2 : 1)) void grouped_gemm_kernel(
     const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter) {
     __shared__ __attribute__((aligned(16))) T smem[TG::LDS_ELEMS];
+    __shared__ int32_t s_begin[kOwnerCap];
     __shared__ int64_t slot;
-    for (int64_t t = blockIdx.x; t < total_tiles; t = next_tile(t, counter, &slot)) {
-        const GroupedDesc &d = descs[find_owner(descs, count, t)];
+    const bool cached = stage_begins<kOwnerCap>(descs, count, total_tiles, s_begin);
+    for (int64_t t = blockIdx.x; t < total_tiles;) {
+        const int ticket = draw_ticket(counter);
+        const GroupedDesc &d = descs[uniform(find_owner(descs, s_begin, cached, count, t))];
         const int64_t local = t - d.tile_begin;
-        const int64_t tm = local / d.tiles_n, tn = local % d.tiles_n;
+        const int64_t tm = uniform(local / d.tiles_n), tn = uniform(local % d.tiles_n);
         const bool vec_ok = (d.lda % TG::VEC == 0) && (d.ldb % TG::VEC == 0) && ((uintptr_t)d.A % 16 == 0) &&
                             ((uintptr_t)d.B % 16 == 0);
         TG::run((const T *)d.A, d.lda, (const T *)d.B, d.ldb, (T *)d.C, d.ldc, d.M, d.N, d.K, tm, tn, vec_ok, smem);
         __syncthreads();
+        t = next_tile(t, counter, ticket, &slot);
     }
 }
 
@@ -70,35 +112,44 @@ template <typename ST>
 __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void grouped_split_gemm_kernel(const GroupedDesc *__restrict__ descs, int count,
                                                                     int64_t total_tiles, int *counter) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
+    __shared__ int32_t s_begin[kOwnerCap];
     __shared__ int64_t slot;
-    for (int64_t t = blockIdx.x; t < total_tiles; t = next_tile(t, counter, &slot)) {
-        const GroupedDesc &d = descs[find_owner(descs, count, t)];
+    const bool cached = stage_begins<kOwnerCap>(descs, count, total_tiles, s_begin);
+    for (int64_t t = blockIdx.x; t < total_tiles;) {
+        const int ticket = draw_ticket(counter);
+        const GroupedDesc &d = descs[uniform(find_owner(descs, s_begin, cached, count, t))];
         const int64_t local = t - d.tile_begin;
-        const int64_t tm = local / d.tiles_n, tn = local % d.tiles_n;
-        const bool vec_ok = (d.K % 8 == 0) && ((uintptr_t)d.A % 16 == 0) && ((uintptr_t)d.B % 16 == 0);
-        ST::run((const uint16_t *)d.A, d.M * d.K, (const uint16_t *)d.B, d.N * d.K, d.C, d.ldc, 0, d.M, d.N, d.K, tm,
-                tn, vec_ok, smem);
+        const int64_t tm = uniform(local / d.tiles_n), tn = uniform(local % d.tiles_n);
+        if constexpr (ST::FUSED) {
+            // descriptors hold the FP32 operands themselves
+            const bool vec_ok = (d.lda % 4 == 0) && ((uintptr_t)d.A % 16 == 0);
+            ST::run_fused((const float *)d.A, d.lda, (const float *)d.B, d.ldb, d.C, d.ldc, 0, d.M, d.N, d.K, tm, tn,
+                          vec_ok, smem);
+        } else {
+            const bool vec_ok = (d.K % 8 == 0) && ((uintptr_t)d.A % 16 == 0) && ((uintptr_t)d.B % 16 == 0);
+            ST::run((const uint16_t *)d.A, d.M * d.K, (const uint16_t *)d.B, d.N * d.K, d.C, d.ldc, 0, d.M, d.N, d.K,
+                    tm, tn, vec_ok, smem);
+        }
         __syncthreads();
+        t = next_tile(t, counter, ticket, &slot);
     }
 }
 
 __global__ __launch_bounds__(256) void grouped_split_kernel(const SplitJob *__restrict__ jobs, int njobs,
                                                             int64_t total_tiles) {
     __shared__ float tile[64][65];
+    __shared__ int32_t s_begin[kJobCap];
     const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const bool cached = stage_begins<kJobCap>(jobs, njobs, total_tiles, s_begin);
     for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
-        int lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (jobs[mid].tile_begin <= t) lo = mid;
-            else hi = mid - 1;
-        }
-        const SplitJob &j = jobs[lo];
+        const SplitJob &j = jobs[uniform(find_owner(jobs, s_begin, cached, njobs, t))];
+        const gptr<const float> X = (gptr<const float>)j.X;
+        const gptr<uint16_t> planes = (gptr<uint16_t>)j.planes;
         const int64_t local = t - j.tile_begin;
         const int64_t r0 = (local / j.tiles_c) * 64, c0 = (local % j.tiles_c) * 64;
         for (int i = ty; i < 64; i += 4) {
             const int64_t r = r0 + i, c = c0 + tx;
-            tile[i][tx] = (r < j.rows && c < j.cols) ? j.X[r * j.ldx + c] : 0.f;
+            tile[i][tx] = (r < j.rows && c < j.cols) ? X[r * j.ldx + c] : 0.f;
         }
         __syncthreads();
         for (int i = ty; i < 64; i += 4) {
@@ -111,7 +162,7 @@ __global__ __launch_bounds__(256) void grouped_split_kernel(const SplitJob *__re
                 const int64_t o = j.transpose ? c * j.ldp + r : r * j.ldp + c;
                 for (int p = 0; p < j.nplanes; ++p) {
                     const uint16_t h = split_bf16_bits(v);
-                    j.planes[p * j.pstride + o] = h;
+                    planes[p * j.pstride + o] = h;
                     v = v - split_bf16_value(h);
                 }
             }
@@ -181,9 +232,12 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // order: problem indices in launch order (schedule already applied).
-void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_method method, int bm, int bn,
+void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_method method, int variant,
                          char *ws, Layout *L) {
-    const bool split = method == MM_SPLIT_BF16_3 || method == MM_SPLIT_BF16_6;
+    const int bm = grouped_tile_bm(method, variant), bn = grouped_tile_bn(method, variant);
+    const bool split_method = method == MM_SPLIT_BF16_3 || method == MM_SPLIT_BF16_6;
+    // fused split tiles read the FP32 operands themselves: no planes, no jobs
+    const bool split = split_method && !split_variant_fused(variant);
     const int np = method == MM_SPLIT_BF16_3 ? 2 : 3;
     L->descs.clear();
     L->jobs.clear();
@@ -339,11 +393,10 @@ static mm_status create_plan(const mm_problem *probs, int32_t count, mm_method m
         p->shapes.push_back(probs[i].K);
     }
     p->order = schedule_order(probs, count, schedule);
-    const int bm = grouped_tile_bm(method, variant), bn = grouped_tile_bn(method, variant);
-    build_layout(probs, p->order, method, bm, bn, nullptr, &p->layout);  // sizing
+    build_layout(probs, p->order, method, variant, nullptr, &p->layout);  // sizing
     hipError_t e = hipSuccess;
     if (p->layout.ws_bytes) e = hipMalloc(&p->ws, p->layout.ws_bytes);
-    if (e == hipSuccess) build_layout(probs, p->order, method, bm, bn, (char *)p->ws, &p->layout);
+    if (e == hipSuccess) build_layout(probs, p->order, method, variant, (char *)p->ws, &p->layout);
     const size_t nd = p->layout.descs.size(), nj = p->layout.jobs.size();
     if (e == hipSuccess && nd) e = hipMalloc(&p->d_descs, nd * sizeof(GroupedDesc));
     if (e == hipSuccess && nj) e = hipMalloc(&p->d_jobs, nj * sizeof(SplitJob));
@@ -385,8 +438,7 @@ static mm_status run_plan(mm_grouped_plan *p, const mm_problem *probs, hipStream
     if (refresh) {
         // Operand pointers may have changed: rebuild descriptors (the workspace
         // and tile map are unchanged) and refresh them in stream order.
-        const int bm = grouped_tile_bm(p->method, p->variant), bn = grouped_tile_bn(p->method, p->variant);
-        build_layout(probs, p->order, p->method, bm, bn, (char *)p->ws, &p->layout);
+        build_layout(probs, p->order, p->method, p->variant, (char *)p->ws, &p->layout);
         const size_t nj = p->layout.jobs.size();
         const int slot = p->ring_pos;
         p->ring_pos = (p->ring_pos + 1) % mm_grouped_plan::RING;
@@ -409,9 +461,8 @@ static mm_status run_plan(mm_grouped_plan *p, const mm_problem *probs, hipStream
 static mm_status run_once(const mm_problem *probs, int32_t count, mm_method method, int variant, int schedule,
                           hipStream_t st) {
     std::vector<int> order = schedule_order(probs, count, schedule);
-    const int bm = grouped_tile_bm(method, variant), bn = grouped_tile_bn(method, variant);
     Layout L;
-    build_layout(probs, order, method, bm, bn, nullptr, &L);
+    build_layout(probs, order, method, variant, nullptr, &L);
     const size_t nd = L.descs.size();
     if (nd == 0) return MM_OK;
     char *buf = nullptr;
@@ -420,7 +471,7 @@ static mm_status run_once(const mm_problem *probs, int32_t count, mm_method meth
     const size_t total = desc_bytes + job_bytes + 256 + L.ws_bytes;
     MM_HIP(hipMallocAsync((void **)&buf, total, st));
     char *ws = buf + desc_bytes + job_bytes + 256;
-    build_layout(probs, order, method, bm, bn, ws, &L);
+    build_layout(probs, order, method, variant, ws, &L);
     GroupedDesc *d_descs = (GroupedDesc *)buf;
     SplitJob *d_jobs = (SplitJob *)(buf + desc_bytes);
     int *d_counter = schedule == 2 ? (int *)(buf + desc_bytes + job_bytes) : nullptr;

@@ -43,6 +43,13 @@ int f32_variant_count();
 TileCfg f32_variant(int v);
 int split_variant_count();
 TileCfg split_variant(int v);
+// Fused split variants read the FP32 operands directly (no plane pass, no
+// workspace); they take row-major operands only.
+bool split_variant_fused(int v);
+hipError_t launch_split_fused(int variant, int nprod, int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
+                              const float *B, int64_t ldb, void *C, int64_t ldc, int c_is_f64, hipStream_t stream);
+// The default plane-reading variant (for transposed operands).
+int default_unfused_split_variant(mm_method method, int64_t M, int64_t N, int64_t K);
 
 // Plain MFMA GEMM (row-major NN), launches on `stream`.
 hipError_t launch_gemm_f64(int variant, int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
@@ -129,9 +136,10 @@ int grouped_tile_bm(mm_method method, int variant);
 int grouped_tile_bn(mm_method method, int variant);
 // Launch order of the problems for a schedule (0: as given; 1, 2: heaviest first).
 std::vector<int> schedule_order(const mm_problem *probs, int count, int schedule);
-// Descriptors (and split jobs with planes carved from `ws`; ws may be null
-// while sizing) of the problems in `order`; empty problems are dropped.
-void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_method method, int bm, int bn,
+// Descriptors (and, for plane-reading split variants, split jobs with planes
+// carved from `ws`; ws may be null while sizing) of the problems in `order`
+// tiled by `variant`; empty problems are dropped.
+void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_method method, int variant,
                   char *ws, Layout *L);
 // Enqueue [grouped split pass] -> [counter reset] -> grouped GEMM for
 // descriptors already in device memory.

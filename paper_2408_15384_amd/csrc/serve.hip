@@ -74,10 +74,13 @@ constexpr int kGroups = 8;  // one grouped launch per (method, size class)
 
 uint64_t elem_bytes(mm_method m) { return m == MM_F64 ? 8 : 4; }
 
-uint64_t request_bytes(const mm_problem &p, mm_method m) {
+// Bytes a request holds while in flight: its operands and result, plus its
+// bfloat16 planes when its variant reads planes (fused split variants make
+// none).
+uint64_t request_bytes(const mm_problem &p, mm_method m, bool planes) {
     const uint64_t e = elem_bytes(m);
     uint64_t b = e * ((uint64_t)p.M * p.K + (uint64_t)p.K * p.N + (uint64_t)p.M * p.N);
-    if ((m == MM_SPLIT_BF16_3 || m == MM_SPLIT_BF16_6) && p.M > 0 && p.N > 0 && p.K > 0)
+    if (planes && (m == MM_SPLIT_BF16_3 || m == MM_SPLIT_BF16_6) && p.M > 0 && p.N > 0 && p.K > 0)
         b += 2 * 256 + split_workspace_bytes(p.M, p.N, p.K, m == MM_SPLIT_BF16_3 ? 3 : 6);
     return b;
 }
@@ -174,7 +177,7 @@ static mm_status launch(mm_server *s, Slot &slot, const std::vector<uint64_t> &i
         if (probs[g].empty()) continue;
         const int variant = s->variant[g];
         order[g] = schedule_order(probs[g].data(), (int)probs[g].size(), 2);
-        build_layout(probs[g].data(), order[g], m, grouped_tile_bm(m, variant), grouped_tile_bn(m, variant), nullptr,
+        build_layout(probs[g].data(), order[g], m, variant, nullptr,
                      &L[g]);
         ws_need += (L[g].ws_bytes + 255) & ~(size_t)255;
     }
@@ -194,7 +197,7 @@ static mm_status launch(mm_server *s, Slot &slot, const std::vector<uint64_t> &i
         const int variant = s->variant[g];
         if (L[g].descs.empty()) continue;
         if (L[g].ws_bytes) {
-            build_layout(probs[g].data(), order[g], m, grouped_tile_bm(m, variant), grouped_tile_bn(m, variant),
+            build_layout(probs[g].data(), order[g], m, variant,
                          slot.ws + ws_off, &L[g]);
             ws_off += (L[g].ws_bytes + 255) & ~(size_t)255;
         }
@@ -339,7 +342,9 @@ mm_status mm_serve_submit(mm_server *s, const mm_problem *req, mm_method method,
         const uint64_t e = elem_bytes(method);
         mm_status st = check_gemm_args(req->M, req->N, req->K, req->A, req->lda, req->B, req->ldb, req->C, req->ldc, e, e);
         if (st != MM_OK) return st;
-        const uint64_t bytes = request_bytes(*req, method);
+        // the size class decides the variant, and the variant whether planes exist
+        const int group = (int)method + (req->M * req->N >= s->large_mn ? 4 : 0);
+        const uint64_t bytes = request_bytes(*req, method, !split_variant_fused(s->variant[group]));
         if (bytes > s->cfg.budget_bytes) return fail(MM_E_NOMEM, "request larger than the server budget");
         std::lock_guard<std::mutex> lock(s->mu);
         if (s->stopping) return fail(MM_E_INVAL, "server is stopping");

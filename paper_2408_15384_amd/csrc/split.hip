@@ -92,6 +92,12 @@ int64_t split_padded_k(int64_t K) { return (K + 31) / 32 * 32; }
 hipError_t launch_split_product(int variant, int nprod, int opa, int opb, int64_t M, int64_t N, int64_t K,
                                 const float *A, int64_t lda, const float *B, int64_t ldb, void *C, int64_t ldc,
                                 int c_is_f64, void *ws, hipStream_t st) {
+    if (split_variant_fused(variant)) {
+        // the fused tile reads row-major FP32 operands; transposed ones take
+        // the plane pass (which transposes) and a plane-reading tile
+        if (!opa && !opb) return launch_split_fused(variant, nprod, M, N, K, A, lda, B, ldb, C, ldc, c_is_f64, st);
+        variant = default_unfused_split_variant(nprod == 3 ? MM_SPLIT_BF16_3 : MM_SPLIT_BF16_6, M, N, K);
+    }
     const int np = nprod == 3 ? 2 : 3;
     const int64_t Kp = split_padded_k(K);
     uint16_t *Ap = (uint16_t *)ws;
@@ -147,17 +153,71 @@ __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void split_gemm_
 }
 
 template <typename ST>
+__global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void split_fused_kernel(
+    const float *__restrict__ A, int64_t lda, const float *__restrict__ B, int64_t ldb, void *C, int64_t ldc,
+    int c_is_f64, int64_t M, int64_t N, int64_t K, int64_t tiles_m, int64_t tiles_n, int vec_ok) {
+    __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
+    int64_t tm, tn;
+    tile_order_split(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
+    ST::run_fused(A, lda, B, ldb, C, ldc, c_is_f64, M, N, K, tm, tn, vec_ok != 0, smem);
+}
+
+template <typename ST>
+static hipError_t launch_fused_tile(int64_t M, int64_t N, int64_t K, const float *A, int64_t lda, const float *B,
+                                    int64_t ldb, void *C, int64_t ldc, int c_is_f64, hipStream_t stream) {
+    if constexpr (!ST::FUSED) {
+        return hipErrorInvalidValue;
+    } else {
+        const int64_t tiles_m = (M + ST::BM - 1) / ST::BM;
+        const int64_t tiles_n = (N + ST::BN - 1) / ST::BN;
+        const int64_t blocks = tiles_m * tiles_n;
+        if (blocks <= 0) return hipSuccess;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+        const int vec_ok = (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
+        hipLaunchKernelGGL((split_fused_kernel<ST>), dim3((unsigned)blocks), dim3(ST::NT), 0, stream, A, lda, B, ldb,
+                           C, ldc, c_is_f64, M, N, K, tiles_m, tiles_n, vec_ok);
+        return hipGetLastError();
+    }
+}
+
+template <typename ST>
 static hipError_t launch_split_tile(int64_t M, int64_t N, int64_t K, const uint16_t *Ap, const uint16_t *Bt, void *C,
                                     int64_t ldc, int c_is_f64, hipStream_t stream) {
-    const int64_t tiles_m = (M + ST::BM - 1) / ST::BM;
-    const int64_t tiles_n = (N + ST::BN - 1) / ST::BN;
-    const int64_t blocks = tiles_m * tiles_n;
-    if (blocks <= 0) return hipSuccess;
-    if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    const int vec_ok = (K % 8 == 0) && ((uintptr_t)Ap % 16 == 0) && ((uintptr_t)Bt % 16 == 0);
-    hipLaunchKernelGGL((split_gemm_kernel<ST>), dim3((unsigned)blocks), dim3(ST::NT), 0, stream, Ap, M * K, Bt,
-                       N * K, C, ldc, c_is_f64, M, N, K, tiles_m, tiles_n, vec_ok);
-    return hipGetLastError();
+    if constexpr (ST::FUSED) {
+        return hipErrorInvalidValue;   // fused tiles take FP32 operands
+    } else {
+        const int64_t tiles_m = (M + ST::BM - 1) / ST::BM;
+        const int64_t tiles_n = (N + ST::BN - 1) / ST::BN;
+        const int64_t blocks = tiles_m * tiles_n;
+        if (blocks <= 0) return hipSuccess;
+        if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+        const int vec_ok = (K % 8 == 0) && ((uintptr_t)Ap % 16 == 0) && ((uintptr_t)Bt % 16 == 0);
+        hipLaunchKernelGGL((split_gemm_kernel<ST>), dim3((unsigned)blocks), dim3(ST::NT), 0, stream, Ap, M * K, Bt,
+                           N * K, C, ldc, c_is_f64, M, N, K, tiles_m, tiles_n, vec_ok);
+        return hipGetLastError();
+    }
+}
+
+#define MM_S_FUSED(id, bm, bn, bk, wm, wn, st) case id: return (st) >= 20;
+bool split_variant_fused(int v) {
+    switch (v) { MM_SPLIT_VARIANTS(MM_S_FUSED) default: return false; }
+}
+
+#define MM_S_FLAUNCH(id, bm, bn, bk, wm, wn, st)                                                                  \
+    case id:                                                                                                       \
+        return nprod == 3 ? launch_fused_tile<SplitTileSel<3, bm, bn, bk, wm, wn, st>::type>(M, N, K, A, lda, B,     \
+                                                                                             ldb, C, ldc, c_is_f64,  \
+                                                                                             stream)                 \
+                          : launch_fused_tile<SplitTileSel<6, bm, bn, bk, wm, wn, st>::type>(M, N, K, A, lda, B,     \
+                                                                                             ldb, C, ldc, c_is_f64,  \
+                                                                                             stream);
+
+hipError_t launch_split_fused(int variant, int nprod, int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
+                              const float *B, int64_t ldb, void *C, int64_t ldc, int c_is_f64, hipStream_t stream) {
+    switch (variant) {
+        MM_SPLIT_VARIANTS(MM_S_FLAUNCH)
+        default: return hipErrorInvalidValue;
+    }
 }
 
 #define MM_S_COUNT(id, bm, bn, bk, wm, wn, st) +1

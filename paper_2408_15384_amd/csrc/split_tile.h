@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gptr.h"
+
 namespace mm {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -42,6 +44,7 @@ template <> struct SplitTerms<6> {
 
 template <int NPROD, int BM_, int BN_, int BK_, int WM_, int WN_, int STAGES_ = 1>
 struct SplitTile {
+    static constexpr bool FUSED = false;
     using Terms = SplitTerms<NPROD>;
     static constexpr int NP = Terms::NP;
     static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_, STAGES = STAGES_;
@@ -69,7 +72,7 @@ struct SplitTile {
     static_assert((NP * BM * VROW) % NT == 0 && (NP * BN * VROW) % NT == 0, "load split");
 
     // planes: base of plane 0, plane p at + p*pstride; rows x K k-contiguous.
-    static __device__ __forceinline__ void load(u16x8 *regs, int nvec, const uint16_t *__restrict__ planes,
+    static __device__ __forceinline__ void load(u16x8 *regs, int nvec, gptr<const uint16_t> planes,
                                                 int64_t pstride, int64_t row0, int64_t nrows_total, int64_t K,
                                                 int64_t k0, int rows_tile, bool vec_ok) {
         const int tid = threadIdx.x;
@@ -80,9 +83,9 @@ struct SplitTile {
             const int r = rem / VROW;
             const int c = (rem % VROW) * 8;
             const int64_t gr = row0 + r;
-            const uint16_t *src = planes + p * pstride + gr * K + k0 + c;
+            gptr<const uint16_t> src = planes + p * pstride + gr * K + k0 + c;
             if (gr < nrows_total && vec_ok && k0 + c + 8 <= K) {
-                regs[i] = *reinterpret_cast<const u16x8 *>(src);
+                regs[i] = *reinterpret_cast<gptr<const u16x8>>(src);
             } else {
                 u16x8 t;
 #pragma unroll
@@ -147,6 +150,7 @@ struct SplitTile {
                                                int64_t ldc, int c_is_f64, int64_t M, int64_t N, int64_t K, int64_t tm,
                                                int64_t tn, bool vec_ok, uint16_t *smem) {
         const int64_t m0 = tm * BM, n0 = tn * BN;
+        const gptr<const uint16_t> Ag = (gptr<const uint16_t>)Ap, Bg = (gptr<const uint16_t>)Bt;
         f32x4 lead[FM][FN], corr[FM][FN];
 #pragma unroll
         for (int fm = 0; fm < FM; ++fm)
@@ -159,16 +163,16 @@ struct SplitTile {
             // One register stage: slice kt+1 is loaded while slice kt is multiplied.
             u16x8 ra[A_VECS], rb[B_VECS];
             const int64_t nkt = (K + BK - 1) / BK;
-            load(ra, A_VECS, Ap, pa_stride, m0, M, K, 0, BM, vec_ok);
-            load(rb, B_VECS, Bt, pb_stride, n0, N, K, 0, BN, vec_ok);
+            load(ra, A_VECS, Ag, pa_stride, m0, M, K, 0, BM, vec_ok);
+            load(rb, B_VECS, Bg, pb_stride, n0, N, K, 0, BN, vec_ok);
             store(smem, A_PLANE, ra, A_VECS, BM);
             store(smem + NP * A_PLANE, B_PLANE, rb, B_VECS, BN);
             __syncthreads();
             for (int64_t kt = 0; kt < nkt; ++kt) {
                 const bool more = kt + 1 < nkt;
                 if (more) {
-                    load(ra, A_VECS, Ap, pa_stride, m0, M, K, (kt + 1) * BK, BM, vec_ok);
-                    load(rb, B_VECS, Bt, pb_stride, n0, N, K, (kt + 1) * BK, BN, vec_ok);
+                    load(ra, A_VECS, Ag, pa_stride, m0, M, K, (kt + 1) * BK, BM, vec_ok);
+                    load(rb, B_VECS, Bg, pb_stride, n0, N, K, (kt + 1) * BK, BN, vec_ok);
                 }
                 const uint16_t *cur = smem + (kt & 1) * STAGE;
                 compute(cur, cur + NP * A_PLANE, lead, corr);
@@ -185,11 +189,11 @@ struct SplitTile {
             // multiplied and slice kt+1 waits in registers for its LDS buffer.
             u16x8 ra0[A_VECS], rb0[B_VECS], ra1[A_VECS], rb1[B_VECS];
             const int64_t nkt = (K + BK - 1) / BK;
-            load(ra0, A_VECS, Ap, pa_stride, m0, M, K, 0, BM, vec_ok);
-            load(rb0, B_VECS, Bt, pb_stride, n0, N, K, 0, BN, vec_ok);
+            load(ra0, A_VECS, Ag, pa_stride, m0, M, K, 0, BM, vec_ok);
+            load(rb0, B_VECS, Bg, pb_stride, n0, N, K, 0, BN, vec_ok);
             if (nkt > 1) {
-                load(ra1, A_VECS, Ap, pa_stride, m0, M, K, BK, BM, vec_ok);
-                load(rb1, B_VECS, Bt, pb_stride, n0, N, K, BK, BN, vec_ok);
+                load(ra1, A_VECS, Ag, pa_stride, m0, M, K, BK, BM, vec_ok);
+                load(rb1, B_VECS, Bg, pb_stride, n0, N, K, BK, BN, vec_ok);
             }
             store(smem, A_PLANE, ra0, A_VECS, BM);
             store(smem + NP * A_PLANE, B_PLANE, rb0, B_VECS, BN);
@@ -197,8 +201,8 @@ struct SplitTile {
             for (int64_t kt = 0; kt < nkt; kt += 2) {
                 // even step kt: register set 1 holds slice kt+1; refill set 0 with kt+2
                 if (kt + 2 < nkt) {
-                    load(ra0, A_VECS, Ap, pa_stride, m0, M, K, (kt + 2) * BK, BM, vec_ok);
-                    load(rb0, B_VECS, Bt, pb_stride, n0, N, K, (kt + 2) * BK, BN, vec_ok);
+                    load(ra0, A_VECS, Ag, pa_stride, m0, M, K, (kt + 2) * BK, BM, vec_ok);
+                    load(rb0, B_VECS, Bg, pb_stride, n0, N, K, (kt + 2) * BK, BN, vec_ok);
                 }
                 compute(smem, smem + NP * A_PLANE, lead, corr);
                 if (kt + 1 < nkt) {
@@ -209,8 +213,8 @@ struct SplitTile {
                 if (kt + 1 >= nkt) break;
                 // odd step kt+1: set 0 holds slice kt+2; refill set 1 with kt+3
                 if (kt + 3 < nkt) {
-                    load(ra1, A_VECS, Ap, pa_stride, m0, M, K, (kt + 3) * BK, BM, vec_ok);
-                    load(rb1, B_VECS, Bt, pb_stride, n0, N, K, (kt + 3) * BK, BN, vec_ok);
+                    load(ra1, A_VECS, Ag, pa_stride, m0, M, K, (kt + 3) * BK, BM, vec_ok);
+                    load(rb1, B_VECS, Bg, pb_stride, n0, N, K, (kt + 3) * BK, BN, vec_ok);
                 }
                 compute(smem + STAGE, smem + STAGE + NP * A_PLANE, lead, corr);
                 if (kt + 2 < nkt) {
@@ -235,8 +239,8 @@ struct SplitTile {
                     const int64_t c = n0 + wn * WN + fn * 16 + li;
                     if (r < M && c < N) {
                         const double val = (double)lead[fm][fn][v] + (double)corr[fm][fn][v];
-                        if (c_is_f64) ((double *)C)[r * ldc + c] = val;
-                        else ((float *)C)[r * ldc + c] = (float)val;
+                        if (c_is_f64) ((gptr<double>)(double *)C)[r * ldc + c] = val;
+                        else ((gptr<float>)(float *)C)[r * ldc + c] = (float)val;
                     }
                 }
     }
@@ -257,6 +261,7 @@ typedef __attribute__((address_space(3))) void mm_lds_void;
 
 template <int NPROD, int BM_, int BN_, int WM_, int WN_, int STAGES_>
 struct SplitTileDirect {
+    static constexpr bool FUSED = false;
     using Terms = SplitTerms<NPROD>;
     static constexpr int NP = Terms::NP;
     static constexpr int BM = BM_, BN = BN_, BK = 32, WM = WM_, WN = WN_, STAGES = STAGES_;
@@ -400,23 +405,178 @@ struct SplitTileDirect {
                     const int64_t c = n0 + wn * WN + fn * 16 + li;
                     if (r < M && c < N) {
                         const double val = (double)lead[fm][fn][v] + (double)corr[fm][fn][v];
-                        if (c_is_f64) ((double *)C)[r * ldc + c] = val;
-                        else ((float *)C)[r * ldc + c] = (float)val;
+                        if (c_is_f64) ((gptr<double>)(double *)C)[r * ldc + c] = val;
+                        else ((gptr<float>)(float *)C)[r * ldc + c] = (float)val;
                     }
                 }
         __syncthreads();   // LDS may be refilled by the next tile of a persistent workgroup
     }
 };
 
+// ---------------------------------------------------------------------------
+// Fused form: the tile reads the FP32 operands themselves and splits them on
+// the way into LDS, so no plane pass runs before the product and no plane
+// workspace exists.  Each K step of 32 is loaded into registers while the
+// previous one is multiplied (as SplitTile with one register stage); a
+// thread owns units of 8 consecutive k of one row of A or one column of B,
+// splits the 8 values into the method's bfloat16 planes exactly as the plane
+// pass does (h = bf16(x), x -= h, plane by plane, in FP32) and writes each
+// plane's 8 values as one 16-byte chunk of the same swizzled LDS layout.
+// The planes, the MFMA sequence and therefore the result are identical to
+// SplitTile's on pre-split planes.  A is read along rows (two 16-byte loads
+// per unit when lda and the base allow it), B down its columns with lanes
+// along N, so every load instruction is coalesced.  Entries past M, N or K
+// read as zero.
+template <int NPROD, int BM_, int BN_, int WM_, int WN_>
+struct SplitTileFused : SplitTile<NPROD, BM_, BN_, 32, WM_, WN_, 1> {
+    static constexpr bool FUSED = true;
+    using Base = SplitTile<NPROD, BM_, BN_, 32, WM_, WN_, 1>;
+    using Base::BM; using Base::BN; using Base::BK; using Base::WM; using Base::WN;
+    using Base::NP; using Base::NWN; using Base::NWAVES; using Base::NT; using Base::FM; using Base::FN;
+    using Base::LD; using Base::A_PLANE; using Base::B_PLANE; using Base::STAGE; using Base::LDS_ELEMS;
+    static constexpr int CHUNKS = BK / 8;                // 8-element units per row
+    static constexpr int A_UNITS = BM * CHUNKS / NT;     // units per thread per K step
+    static constexpr int B_UNITS = BN * CHUNKS / NT;
+    static_assert((BM * CHUNKS) % NT == 0 && (BN * CHUNKS) % NT == 0, "units must split evenly");
+
+    static __device__ __forceinline__ void load_a(float (&ra)[A_UNITS][8], gptr<const float> A, int64_t lda,
+                                                  int64_t m0, int64_t M, int64_t K, int64_t k0, bool vec_ok) {
+#pragma unroll
+        for (int i = 0; i < A_UNITS; ++i) {
+            const int u = threadIdx.x + i * NT;
+            const int64_t r = m0 + u / CHUNKS;
+            const int64_t k = k0 + (u % CHUNKS) * 8;
+            gptr<const float> p = A + r * lda + k;
+            if (r < M && vec_ok && k + 8 <= K) {
+                const f32x4 x = *reinterpret_cast<gptr<const f32x4>>(p);
+                const f32x4 y = *reinterpret_cast<gptr<const f32x4>>(p + 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    ra[i][e] = x[e];
+                    ra[i][4 + e] = y[e];
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) ra[i][e] = (r < M && k + e < K) ? p[e] : 0.f;
+            }
+        }
+    }
+
+    static __device__ __forceinline__ void load_b(float (&rb)[B_UNITS][8], gptr<const float> B, int64_t ldb,
+                                                  int64_t n0, int64_t N, int64_t K, int64_t k0) {
+#pragma unroll
+        for (int i = 0; i < B_UNITS; ++i) {
+            const int u = threadIdx.x + i * NT;
+            const int64_t n = n0 + u % BN;
+            const int64_t k = k0 + (u / BN) * 8;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) rb[i][e] = (n < N && k + e < K) ? B[(k + e) * ldb + n] : 0.f;
+        }
+    }
+
+    // Split 8 values into the planes and write them to LDS: plane p of the
+    // operand starts at base + p * plane_elems; (row, chunk) is the unit.
+    static __device__ __forceinline__ void put(uint16_t *base, int plane_elems, int row, int chunk,
+                                               const float (&v)[8]) {
+        float x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = v[e];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            u16x8 h;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                h[e] = split_bf16_bits(x[e]);
+                x[e] = x[e] - split_bf16_value(h[e]);
+            }
+            *reinterpret_cast<u16x8 *>(base + p * plane_elems + row * LD + Base::swz(row, chunk) * 8) = h;
+        }
+    }
+
+    static __device__ __forceinline__ void put_all(uint16_t *stage, const float (&ra)[A_UNITS][8],
+                                                   const float (&rb)[B_UNITS][8]) {
+#pragma unroll
+        for (int i = 0; i < A_UNITS; ++i) {
+            const int u = threadIdx.x + i * NT;
+            put(stage, A_PLANE, u / CHUNKS, u % CHUNKS, ra[i]);
+        }
+#pragma unroll
+        for (int i = 0; i < B_UNITS; ++i) {
+            const int u = threadIdx.x + i * NT;
+            put(stage + NP * A_PLANE, B_PLANE, u % BN, u / BN, rb[i]);
+        }
+    }
+
+    // Tile (tm, tn) of C = A.B for FP32 A (M x K, row-major, lda) and B
+    // (K x N, row-major, ldb); vec_ok: lda % 4 == 0 and A 16-byte aligned.
+    static __device__ __forceinline__ void run_fused(const float *A_, int64_t lda, const float *B_, int64_t ldb,
+                                                     void *C, int64_t ldc, int c_is_f64, int64_t M, int64_t N,
+                                                     int64_t K, int64_t tm, int64_t tn, bool vec_ok, uint16_t *smem) {
+        const int64_t m0 = tm * BM, n0 = tn * BN;
+        const gptr<const float> A = (gptr<const float>)A_, B = (gptr<const float>)B_;
+        f32x4 lead[FM][FN], corr[FM][FN];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) {
+                lead[fm][fn] = f32x4{0, 0, 0, 0};
+                corr[fm][fn] = f32x4{0, 0, 0, 0};
+            }
+        float ra[A_UNITS][8], rb[B_UNITS][8];
+        const int64_t nkt = (K + BK - 1) / BK;
+        if (nkt > 0) {
+            load_a(ra, A, lda, m0, M, K, 0, vec_ok);
+            load_b(rb, B, ldb, n0, N, K, 0);
+            put_all(smem, ra, rb);
+        }
+        __syncthreads();
+        for (int64_t kt = 0; kt < nkt; ++kt) {
+            const bool more = kt + 1 < nkt;
+            if (more) {
+                load_a(ra, A, lda, m0, M, K, (kt + 1) * BK, vec_ok);
+                load_b(rb, B, ldb, n0, N, K, (kt + 1) * BK);
+            }
+            const uint16_t *cur = smem + (kt & 1) * STAGE;
+            Base::compute(cur, cur + NP * A_PLANE, lead, corr);
+            if (more) put_all(smem + ((kt + 1) & 1) * STAGE, ra, rb);
+            __syncthreads();
+        }
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int wm = wave / NWN, wn = wave % NWN;
+        const int li = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t r = m0 + wm * WM + fm * 16 + q * 4 + v;
+                    const int64_t c = n0 + wn * WN + fn * 16 + li;
+                    if (r < M && c < N) {
+                        const double val = (double)lead[fm][fn][v] + (double)corr[fm][fn][v];
+                        if (c_is_f64) ((gptr<double>)(double *)C)[r * ldc + c] = val;
+                        else ((gptr<float>)(float *)C)[r * ldc + c] = (float)val;
+                    }
+                }
+    }
+};
+
 // Variant selector: S = 1, 2 register stages (SplitTile); S = 10 + b: direct
-// global-to-LDS ring of b buffers (SplitTileDirect, BK = 32).
-template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool DIRECT = (S >= 10)>
+// global-to-LDS ring of b buffers (SplitTileDirect, BK = 32); S = 20: fused
+// split (SplitTileFused, BK = 32, FP32 operands, no plane pass).
+template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, int KIND = (S >= 20 ? 2 : S >= 10 ? 1 : 0)>
 struct SplitTileSel {
     typedef SplitTile<NPROD, BM, BN, BK, WM, WN, S> type;
 };
 template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S>
-struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, true> {
+struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, 1> {
     typedef SplitTileDirect<NPROD, BM, BN, WM, WN, S - 10> type;
+};
+template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S>
+struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, 2> {
+    static_assert(BK == 32, "the fused tile steps K by 32");
+    typedef SplitTileFused<NPROD, BM, BN, WM, WN> type;
 };
 
 }  // namespace mm

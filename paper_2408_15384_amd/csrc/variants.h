@@ -28,7 +28,9 @@
 
 // Split variants carry a seventh field, S: 1 or 2 register stages of global
 // prefetch, or 10 + b: a ring of b LDS buffers fed by direct global-to-LDS
-// loads (BK 32).
+// loads (BK 32) -- all three read bfloat16 planes made by a split pass -- or
+// 20: the fused tile, which reads the FP32 operands and splits them on the
+// way into LDS (BK 32, no plane pass, no workspace).
 #define MM_SPLIT_VARIANTS(X)          \
     X(0, 128, 128, 32, 64, 64, 1)     \
     X(1, 64, 64, 32, 32, 32, 1)       \
@@ -39,4 +41,8 @@
     X(6, 128, 128, 32, 64, 32, 13)    \
     X(7, 128, 128, 32, 64, 64, 13)    \
     X(8, 64, 64, 32, 32, 32, 13)      \
-    X(9, 256, 128, 32, 64, 64, 12)
+    X(9, 256, 128, 32, 64, 64, 12)    \
+    X(10, 64, 64, 32, 32, 32, 20)     \
+    X(11, 128, 64, 32, 64, 32, 20)    \
+    X(12, 128, 128, 32, 64, 32, 20)   \
+    X(13, 128, 128, 32, 64, 64, 20)

@@ -226,6 +226,36 @@ def test_split_explicit_workspace_and_variants(mm):
         assert np.all(np.abs(host(C) - E) <= bound)
 
 
+@pytest.mark.parametrize("nprod", [3, 6])
+@pytest.mark.parametrize("shape", [(300, 270, 333), (64, 64, 32), (129, 7, 70), (1, 1, 1), (33, 65, 1000)])
+def test_split_variants_bit_identical(mm, nprod, shape):
+    """Every split variant -- planes read by registers or by direct loads, or
+    the fused tile that splits the FP32 operands itself -- sums the same plane
+    products in the same order, so all results are equal bit for bit."""
+    M, N, K = shape
+    method = f"split{nprod}"
+    A, B = I.pair("uniform_f32", M, N, K, seed=M + N)
+    dA, dB = dev(A), dev(B)
+    # the same operands behind a misaligned base and padded leading dimensions
+    pa = torch.zeros((M, K + 3), dtype=torch.float32, device="cuda")
+    pb = torch.zeros((K, N + 5), dtype=torch.float32, device="cuda")
+    pa[:, 1:K + 1] = dA
+    pb[:, 2:N + 2] = dB
+    vA, vB = pa[:, 1:K + 1], pb[:, 2:N + 2]
+    ref = None
+    for v in range(mm.variant_count(method)):
+        for a, b in ((dA, dB), (vA, vB)):
+            C = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
+            mm.gemm_variant(method, v, a, b, C)
+            Ch = host(C)
+            if ref is None:
+                ref = Ch
+            assert np.array_equal(Ch, ref), f"variant {v} {mm.variant_info(method, v)}"
+    E = oracle.split_product(A, B, nprod)
+    bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F32) + 2.0 ** -24 * np.abs(E)
+    assert np.all(np.abs(ref - E) <= bound)
+
+
 # ------------------------------------------------------------------ residual
 
 def test_residual_exact_and_planted(mm):

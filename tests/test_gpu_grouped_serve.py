@@ -88,6 +88,22 @@ def test_grouped_equals_single_every_schedule(mm, method):
     check_oracle(method, hostAB, Cs, range(len(shapes)))
 
 
+@pytest.mark.parametrize("method", ["split3", "split6"])
+def test_grouped_every_split_variant(mm, method):
+    # plane-reading and fused variants alike: grouped == single, bit for bit
+    shapes = ragged_shapes(24, 1, 300, seed=21)
+    As, Bs, Cs, hostAB = make_batch(method, shapes, seed=22)
+    for variant in range(mm.variant_count(method)):
+        ref = singles(mm, method, variant, As, Bs)
+        for C in Cs:
+            C.fill_(float("nan"))
+        mm.gemm_grouped(method, As, Bs, Cs, variant=variant, schedule=2)
+        torch.cuda.synchronize()
+        for i, C in enumerate(Cs):
+            assert np.array_equal(C.cpu().numpy(), ref[i]), f"variant {variant} problem {i}"
+    check_oracle(method, hostAB, Cs, range(len(shapes)))
+
+
 @pytest.mark.parametrize("method", ["f64", "split6"])
 def test_plan_graph_replay(mm, method):
     shapes = ragged_shapes(24, 8, 260, seed=3)
