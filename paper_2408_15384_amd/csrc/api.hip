@@ -57,7 +57,8 @@ void retain_default_pool() {
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
         uint64_t keep = UINT64_MAX;
-        hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+        // best effort: without it the pool only returns memory more eagerly
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
     }
     done.push_back(dev);
 }

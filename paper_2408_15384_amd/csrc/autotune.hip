@@ -191,7 +191,10 @@ mm_status mm_autotune(mm_method method, int64_t M, int64_t N, int64_t K, const v
                     break;
                 }
                 float ms = 0;
-                hipEventElapsedTime(&ms, e0, e1);
+                if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                    status = MM_E_DEVICE;
+                    break;
+                }
                 if (r >= warmup) times.push_back(ms);
             }
             if (status != MM_OK) break;
@@ -202,9 +205,10 @@ mm_status mm_autotune(mm_method method, int64_t M, int64_t N, int64_t K, const v
                 best_ms = med;
             }
         }
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
-        if (ws) hipFree(ws);
+        // best-effort cleanup: a failure here cannot change the measurement
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (ws) (void)hipFree(ws);
         if (status != MM_OK) return status;
         {
             std::lock_guard<std::mutex> lock(g_mu);
@@ -248,12 +252,15 @@ mm_status mm_grouped_autotune(const mm_problem *probs, int32_t count, mm_method 
                         break;
                     }
                     float ms = 0;
-                    hipEventElapsedTime(&ms, e0, e1);
+                    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        status = MM_E_DEVICE;
+                        break;
+                    }
                     if (r >= warmup) times.push_back(ms);
                 }
                 if (plan) {
-                    hipStreamSynchronize(st);
-                    mm_grouped_plan_destroy(plan);
+                    if (hipStreamSynchronize(st) != hipSuccess) status = MM_E_DEVICE;
+                    (void)mm_grouped_plan_destroy(plan);
                 }
                 if (status != MM_OK) break;
                 std::sort(times.begin(), times.end());
@@ -265,8 +272,8 @@ mm_status mm_grouped_autotune(const mm_problem *probs, int32_t count, mm_method 
                 }
             }
         }
-        hipEventDestroy(e0);
-        hipEventDestroy(e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
         if (status != MM_OK) return status;
         store_grouped(probs, count, method, best_v, best_s, best_ms);
         if (variant_out) *variant_out = best_v;

@@ -88,8 +88,10 @@ __device__ __forceinline__ int64_t next_tile(int64_t cur, const int *counter, in
     return uniform(*slot);
 }
 
+// Two waves per SIMD are asked of 4-wave tiles whose LDS lets two workgroups
+// share a CU; otherwise one.
 template <typename TG, typename T>
-__global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 ? 2 : 1)) void grouped_gemm_kernel(
+__global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 && TG::LDS_ELEMS * sizeof(T) <= 76 * 1024 ? 2 : 1)) void grouped_gemm_kernel(
     const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter) {
     __shared__ __attribute__((aligned(16))) T smem[TG::LDS_ELEMS];
     __shared__ int32_t s_begin[kOwnerCap];
@@ -211,7 +213,7 @@ static int persistent_grid(mm_method method, int variant, KernelPtr fn, int nt) 
     static std::mutex mu;
     static std::map<std::pair<int, int>, int> cache;
     int dev = 0;
-    hipGetDevice(&dev);
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     std::lock_guard<std::mutex> lock(mu);
     auto key = std::make_pair(dev * 64 + (int)method, variant);
     auto it = cache.find(key);
@@ -362,21 +364,23 @@ struct mm_grouped_plan {
 
 namespace mm {
 
+// Releases everything a plan owns.  Best effort: a failing release (after a
+// device error) must not stop the others, so return codes are not acted on.
 static void destroy_plan(mm_grouped_plan *p) {
     if (!p) return;
-    if (p->exec) hipGraphExecDestroy(p->exec);
-    if (p->graph) hipGraphDestroy(p->graph);
-    if (p->capture_stream) hipStreamDestroy(p->capture_stream);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
     for (auto &e : p->ring_ev)
         if (e) {
-            hipEventSynchronize(e);
-            hipEventDestroy(e);
+            (void)hipEventSynchronize(e);   // the pinned ring may still feed a copy
+            (void)hipEventDestroy(e);
         }
-    if (p->h_ring) hipHostFree(p->h_ring);
-    if (p->d_descs) hipFree(p->d_descs);
-    if (p->d_jobs) hipFree(p->d_jobs);
-    if (p->d_counter) hipFree(p->d_counter);
-    if (p->ws) hipFree(p->ws);
+    if (p->h_ring) (void)hipHostFree(p->h_ring);
+    if (p->d_descs) (void)hipFree(p->d_descs);
+    if (p->d_jobs) (void)hipFree(p->d_jobs);
+    if (p->d_counter) (void)hipFree(p->d_counter);
+    if (p->ws) (void)hipFree(p->ws);
     delete p;
 }
 
@@ -386,7 +390,7 @@ static mm_status create_plan(const mm_problem *probs, int32_t count, mm_method m
     p->method = method;
     p->variant = variant;
     p->schedule = schedule;
-    hipGetDevice(&p->device);
+    hipError_t e = hipGetDevice(&p->device);
     for (int i = 0; i < count; ++i) {
         p->shapes.push_back(probs[i].M);
         p->shapes.push_back(probs[i].N);
@@ -394,8 +398,7 @@ static mm_status create_plan(const mm_problem *probs, int32_t count, mm_method m
     }
     p->order = schedule_order(probs, count, schedule);
     build_layout(probs, p->order, method, variant, nullptr, &p->layout);  // sizing
-    hipError_t e = hipSuccess;
-    if (p->layout.ws_bytes) e = hipMalloc(&p->ws, p->layout.ws_bytes);
+    if (e == hipSuccess && p->layout.ws_bytes) e = hipMalloc(&p->ws, p->layout.ws_bytes);
     if (e == hipSuccess) build_layout(probs, p->order, method, variant, (char *)p->ws, &p->layout);
     const size_t nd = p->layout.descs.size(), nj = p->layout.jobs.size();
     if (e == hipSuccess && nd) e = hipMalloc(&p->d_descs, nd * sizeof(GroupedDesc));
