@@ -295,9 +295,9 @@ def test_f64_paper_sizes_box_muller(mm, n):
 
 # ------------------------------------------------------------------ full size
 
+@pytest.mark.parametrize("n", [4096, 8192])
 @pytest.mark.parametrize("kind", ["uniform_f64", "int_f64"])
-def test_f64_8192_sampled(mm, kind):
-    n = 8192
+def test_f64_full_size_sampled(mm, kind, n):
     A, B = I.pair(kind, n, n, n, seed=0)
     C = host(mm.gemm_f64(dev(A), dev(B)))
     rng = np.random.default_rng(99)
@@ -310,3 +310,29 @@ def test_f64_8192_sampled(mm, kind):
     else:
         absref = oracle.gemm_entries(np.abs(A), np.abs(B), rows, cols)
         assert np.all(np.abs(got - ref) <= 4 * n * oracle.U_F64 * absref)
+
+
+@pytest.mark.parametrize("kind", ["uniform_f32", "m2e_f32"])
+def test_f32_and_split_8192_rows(mm, kind):
+    """Precision configuration at full size, default variants: three whole rows
+    of the FP32 and split products against the oracle -- per entry against the
+    split emulation, normwise against the exact product (<= 1e-6 where the
+    method reaches it: 3 planes always, 2 planes on the positive m*2^e set)."""
+    n = 8192
+    A, B = I.pair(kind, n, n, n, seed=0)
+    dA, dB = dev(A), dev(B)
+    rows = [0, 4095, n - 1]
+    Ar = A[rows]
+    R = oracle.gemm(Ar, B)
+    absR = oracle.abs_product(Ar, B)
+    C32 = host(mm.gemm_f32(dA, dB))[rows]
+    assert np.all(np.abs(C32 - R) <= oracle.elementwise_bound(absR, n, oracle.U_F32))
+    for nprod in (3, 6):
+        C = host(mm.gemm_split_bf16(dA, dB, nprod=nprod))[rows].astype(np.float64)
+        E = oracle.split_product(Ar, B, nprod)
+        assert np.all(np.abs(C - E) <= oracle.elementwise_bound(absR, n, oracle.U_F32) + 2.0 ** -24 * np.abs(E))
+        err = oracle.normwise_rel(C, R)
+        if nprod == 6 or kind == "m2e_f32":
+            assert err <= 1e-6, (nprod, kind, err)
+        else:
+            assert err <= 1e-5, (nprod, kind, err)
