@@ -82,21 +82,25 @@ struct TileGemm {
 
     typedef typename MfmaOp<T>::acc_t acc_t;
     typedef typename MfmaOp<T>::vec_t vec_t;
+    // The same 16 bytes at element alignment: the global loads take any base
+    // and leading dimension (the HSA runtime runs the memory system in
+    // unaligned mode, and the compiler emits one 16-byte load for it).
+    typedef vec_t vec_ua __attribute__((aligned(sizeof(T))));
 
     // Global -> registers for the slice starting at k0.  Out-of-range elements
-    // (beyond M, N or K) read as zero so ragged edges add nothing.
+    // (beyond M, N or K) read as zero so ragged edges add nothing; a 16-byte
+    // chunk wholly in range is one vector load.
     static __device__ __forceinline__ void load_a(vec_t (&ra)[A_VECS], gptr<const T> A, int64_t lda,
-                                                  int rows_left, int64_t K, int64_t k0, bool vec_ok) {
+                                                  int rows_left, int64_t K, int64_t k0) {
         const int tid = threadIdx.x;
-        const bool kfull = vec_ok && (k0 + BK <= K);
 #pragma unroll
         for (int i = 0; i < A_VECS; ++i) {
             const int v = tid + i * NT;
             const int r = v / AV_ROW;
             const int c = (v % AV_ROW) * VEC;
             gptr<const T> p = A + (int64_t)r * lda + k0 + c;
-            if (r < rows_left && kfull) {
-                ra[i] = *reinterpret_cast<gptr<const vec_t>>(p);
+            if (r < rows_left && k0 + c + VEC <= K) {
+                ra[i] = *reinterpret_cast<gptr<const vec_ua>>(p);
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
@@ -106,7 +110,7 @@ struct TileGemm {
     }
 
     static __device__ __forceinline__ void load_b(vec_t (&rb)[B_VECS], gptr<const T> B, int64_t ldb,
-                                                  int cols_left, int64_t K, int64_t k0, bool vec_ok) {
+                                                  int cols_left, int64_t K, int64_t k0) {
         const int tid = threadIdx.x;
 #pragma unroll
         for (int i = 0; i < B_VECS; ++i) {
@@ -115,8 +119,8 @@ struct TileGemm {
             const int c = (v % BV_ROW) * VEC;
             gptr<const T> p = B + (k0 + r) * ldb + c;
             const bool krow = (k0 + r < K);
-            if (krow && vec_ok && c + VEC <= cols_left) {
-                rb[i] = *reinterpret_cast<gptr<const vec_t>>(p);
+            if (krow && c + VEC <= cols_left) {
+                rb[i] = *reinterpret_cast<gptr<const vec_ua>>(p);
             } else {
 #pragma unroll
                 for (int e = 0; e < VEC; ++e)
@@ -176,11 +180,13 @@ struct TileGemm {
     }
 
     // The whole tile (tm, tn): C[tm*BM.., tn*BN..] = A[tm*BM.., :] . B[:, tn*BN..].
-    // `smem` holds LDS_ELEMS elements.  vec_ok: leading dimensions and bases
-    // allow 16-byte vector access.
+    // `smem` holds LDS_ELEMS elements.  vec_ok (whether leading dimensions and
+    // bases are 16-byte multiples) is part of the shared tile interface; this
+    // body does not need it, since its vector loads are element-aligned.
     static __device__ __forceinline__ void run(const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
                                                int64_t ldb, T *__restrict__ C, int64_t ldc, int64_t M, int64_t N,
                                                int64_t K, int64_t tm, int64_t tn, bool vec_ok, T *smem) {
+        (void)vec_ok;
         const int64_t m0 = tm * BM, n0 = tn * BN;
         const int rows_left = (int)((M - m0) < BM ? (M - m0) : BM);
         const int cols_left = (int)((N - n0) < BN ? (N - n0) : BN);
@@ -198,16 +204,16 @@ struct TileGemm {
         vec_t ra[A_VECS], rb[B_VECS];
         const int64_t nkt = (K + BK - 1) / BK;
         constexpr int STAGE = A_STAGE + B_STAGE;
-        load_a(ra, Ab, lda, rows_left, K, 0, vec_ok);
-        load_b(rb, Bb, ldb, cols_left, K, 0, vec_ok);
+        load_a(ra, Ab, lda, rows_left, K, 0);
+        load_b(rb, Bb, ldb, cols_left, K, 0);
         store_a(smem, ra);
         store_b(smem + A_STAGE, rb);
         __syncthreads();
         for (int64_t kt = 0; kt < nkt; ++kt) {
             const bool more = kt + 1 < nkt;
             if (more) {
-                load_a(ra, Ab, lda, rows_left, K, (kt + 1) * BK, vec_ok);
-                load_b(rb, Bb, ldb, cols_left, K, (kt + 1) * BK, vec_ok);
+                load_a(ra, Ab, lda, rows_left, K, (kt + 1) * BK);
+                load_b(rb, Bb, ldb, cols_left, K, (kt + 1) * BK);
             }
             const T *cur = smem + (kt & 1) * STAGE;
             T *nxt = smem + ((kt + 1) & 1) * STAGE;

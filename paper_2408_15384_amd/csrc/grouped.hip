@@ -124,9 +124,8 @@ __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void grouped_spl
         const int64_t tm = uniform(local / d.tiles_n), tn = uniform(local % d.tiles_n);
         if constexpr (ST::FUSED) {
             // descriptors hold the FP32 operands themselves
-            const bool vec_ok = (d.lda % 4 == 0) && ((uintptr_t)d.A % 16 == 0);
             ST::run_fused((const float *)d.A, d.lda, (const float *)d.B, d.ldb, d.C, d.ldc, 0, d.M, d.N, d.K, tm, tn,
-                          vec_ok, smem);
+                          smem);
         } else {
             const bool vec_ok = (d.K % 8 == 0) && ((uintptr_t)d.A % 16 == 0) && ((uintptr_t)d.B % 16 == 0);
             ST::run((const uint16_t *)d.A, d.M * d.K, (const uint16_t *)d.B, d.N * d.K, d.C, d.ldc, 0, d.M, d.N, d.K,

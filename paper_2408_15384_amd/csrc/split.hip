@@ -155,11 +155,11 @@ __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void split_gemm_
 template <typename ST>
 __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void split_fused_kernel(
     const float *__restrict__ A, int64_t lda, const float *__restrict__ B, int64_t ldb, void *C, int64_t ldc,
-    int c_is_f64, int64_t M, int64_t N, int64_t K, int64_t tiles_m, int64_t tiles_n, int vec_ok) {
+    int c_is_f64, int64_t M, int64_t N, int64_t K, int64_t tiles_m, int64_t tiles_n) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
     int64_t tm, tn;
     tile_order_split(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
-    ST::run_fused(A, lda, B, ldb, C, ldc, c_is_f64, M, N, K, tm, tn, vec_ok != 0, smem);
+    ST::run_fused(A, lda, B, ldb, C, ldc, c_is_f64, M, N, K, tm, tn, smem);
 }
 
 template <typename ST>
@@ -173,9 +173,8 @@ static hipError_t launch_fused_tile(int64_t M, int64_t N, int64_t K, const float
         const int64_t blocks = tiles_m * tiles_n;
         if (blocks <= 0) return hipSuccess;
         if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-        const int vec_ok = (lda % 4 == 0) && ((uintptr_t)A % 16 == 0);
         hipLaunchKernelGGL((split_fused_kernel<ST>), dim3((unsigned)blocks), dim3(ST::NT), 0, stream, A, lda, B, ldb,
-                           C, ldc, c_is_f64, M, N, K, tiles_m, tiles_n, vec_ok);
+                           C, ldc, c_is_f64, M, N, K, tiles_m, tiles_n);
         return hipGetLastError();
     }
 }

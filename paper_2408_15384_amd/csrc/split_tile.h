@@ -423,10 +423,10 @@ struct SplitTileDirect {
 // pass does (h = bf16(x), x -= h, plane by plane, in FP32) and writes each
 // plane's 8 values as one 16-byte chunk of the same swizzled LDS layout.
 // The planes, the MFMA sequence and therefore the result are identical to
-// SplitTile's on pre-split planes.  A is read along rows (two 16-byte loads
-// per unit when lda and the base allow it), B down its columns with lanes
-// along N, so every load instruction is coalesced.  Entries past M, N or K
-// read as zero.
+// SplitTile's on pre-split planes.  A is read along rows (two element-aligned
+// 16-byte loads per unit wholly inside K, whatever lda and the base), B down
+// its columns with lanes along N, so every load instruction is coalesced.
+// Entries past M, N or K read as zero.
 template <int NPROD, int BM_, int BN_, int WM_, int WN_>
 struct SplitTileFused : SplitTile<NPROD, BM_, BN_, 32, WM_, WN_, 1> {
     static constexpr bool FUSED = true;
@@ -440,16 +440,18 @@ struct SplitTileFused : SplitTile<NPROD, BM_, BN_, 32, WM_, WN_, 1> {
     static_assert((BM * CHUNKS) % NT == 0 && (BN * CHUNKS) % NT == 0, "units must split evenly");
 
     static __device__ __forceinline__ void load_a(float (&ra)[A_UNITS][8], gptr<const float> A, int64_t lda,
-                                                  int64_t m0, int64_t M, int64_t K, int64_t k0, bool vec_ok) {
+                                                  int64_t m0, int64_t M, int64_t K, int64_t k0) {
 #pragma unroll
         for (int i = 0; i < A_UNITS; ++i) {
             const int u = threadIdx.x + i * NT;
             const int64_t r = m0 + u / CHUNKS;
             const int64_t k = k0 + (u % CHUNKS) * 8;
             gptr<const float> p = A + r * lda + k;
-            if (r < M && vec_ok && k + 8 <= K) {
-                const f32x4 x = *reinterpret_cast<gptr<const f32x4>>(p);
-                const f32x4 y = *reinterpret_cast<gptr<const f32x4>>(p + 4);
+            if (r < M && k + 8 <= K) {
+                // element-aligned 16-byte loads: any lda and base (unaligned mode)
+                typedef f32x4 f32x4_ua __attribute__((aligned(4)));
+                const f32x4 x = *reinterpret_cast<gptr<const f32x4_ua>>(p);
+                const f32x4 y = *reinterpret_cast<gptr<const f32x4_ua>>(p + 4);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
                     ra[i][e] = x[e];
@@ -508,10 +510,10 @@ struct SplitTileFused : SplitTile<NPROD, BM_, BN_, 32, WM_, WN_, 1> {
     }
 
     // Tile (tm, tn) of C = A.B for FP32 A (M x K, row-major, lda) and B
-    // (K x N, row-major, ldb); vec_ok: lda % 4 == 0 and A 16-byte aligned.
+    // (K x N, row-major, ldb); any lda, ldb and base alignment.
     static __device__ __forceinline__ void run_fused(const float *A_, int64_t lda, const float *B_, int64_t ldb,
                                                      void *C, int64_t ldc, int c_is_f64, int64_t M, int64_t N,
-                                                     int64_t K, int64_t tm, int64_t tn, bool vec_ok, uint16_t *smem) {
+                                                     int64_t K, int64_t tm, int64_t tn, uint16_t *smem) {
         const int64_t m0 = tm * BM, n0 = tn * BN;
         const gptr<const float> A = (gptr<const float>)A_, B = (gptr<const float>)B_;
         f32x4 lead[FM][FN], corr[FM][FN];
@@ -525,7 +527,7 @@ struct SplitTileFused : SplitTile<NPROD, BM_, BN_, 32, WM_, WN_, 1> {
         float ra[A_UNITS][8], rb[B_UNITS][8];
         const int64_t nkt = (K + BK - 1) / BK;
         if (nkt > 0) {
-            load_a(ra, A, lda, m0, M, K, 0, vec_ok);
+            load_a(ra, A, lda, m0, M, K, 0);
             load_b(rb, B, ldb, n0, N, K, 0);
             put_all(smem, ra, rb);
         }
@@ -533,7 +535,7 @@ struct SplitTileFused : SplitTile<NPROD, BM_, BN_, 32, WM_, WN_, 1> {
         for (int64_t kt = 0; kt < nkt; ++kt) {
             const bool more = kt + 1 < nkt;
             if (more) {
-                load_a(ra, A, lda, m0, M, K, (kt + 1) * BK, vec_ok);
+                load_a(ra, A, lda, m0, M, K, (kt + 1) * BK);
                 load_b(rb, B, ldb, n0, N, K, (kt + 1) * BK);
             }
             const uint16_t *cur = smem + (kt & 1) * STAGE;

@@ -15,7 +15,9 @@
     X(3, 128, 64, 16, 64, 32, 0)      \
     X(4, 256, 128, 16, 64, 64, 13)    \
     X(5, 128, 128, 16, 64, 64, 13)    \
-    X(6, 64, 64, 16, 32, 32, 13)
+    X(6, 64, 64, 16, 32, 32, 13)      \
+    X(7, 64, 64, 16, 32, 32, 12)      \
+    X(8, 128, 64, 16, 64, 32, 13)
 
 #define MM_F32_VARIANTS(X)            \
     X(0, 128, 128, 16, 64, 64, 0)     \
@@ -24,7 +26,10 @@
     X(3, 128, 128, 32, 64, 64, 0)     \
     X(4, 256, 128, 32, 64, 64, 13)    \
     X(5, 256, 128, 16, 64, 64, 13)    \
-    X(6, 64, 64, 32, 32, 32, 13)
+    X(6, 64, 64, 32, 32, 32, 13)      \
+    X(7, 64, 64, 16, 32, 32, 13)      \
+    X(8, 64, 64, 32, 32, 32, 12)      \
+    X(9, 128, 64, 32, 64, 32, 13)
 
 // Split variants carry a seventh field, S: 1 or 2 register stages of global
 // prefetch, or 10 + b: a ring of b LDS buffers fed by direct global-to-LDS
