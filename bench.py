@@ -16,10 +16,12 @@ Also reported in the same line (context, not the headline):
     input sets, each with its error against the binary64 oracle (sampled rows)
     and its binary64 residual probe;
   * grouped: 512 FP32 problems with dimensions log-uniform on [32, 1024], one
-    graph-replayed persistent launch, plain FP32 versus split;
+    graph-replayed persistent launch, plain FP32 versus split, with the
+    residual probe of every result and the oracle's error on a sample;
   * serving: Poisson arrivals of GEMM requests (dimensions log-uniform on
     [64, 4096], half binary64, half FP32-accurate split), operands resident on
-    the device, a 64 GiB admission budget; p50/p99 latency and throughput.
+    the device, a 64 GiB admission budget; p50/p99 latency and throughput,
+    the residual probe of every result;
 
   * strassen: one Strassen-Winograd level on the binary64 product at 8192;
   * shard: one GPU's share (1024 rows) of a row-sharded 8192 product;
@@ -196,6 +198,10 @@ def grouped_section(torch, mm, reps=10):
         Cs.append(torch.empty((M, N), dtype=torch.float32, device="cuda"))
         flop += 2.0 * M * N * K
     out = {"problems": 512, "flop": flop}
+    import oracle
+    x_all = torch.from_numpy(I.probe_vector(1024)).cuda()
+    rws = torch.empty(mm.lib().mm_residual_workspace_bytes(1024, 1024, 1024), dtype=torch.uint8, device="cuda")
+    sample = sorted(np.random.default_rng(4).choice(len(shapes), size=8, replace=False).tolist())
     for method, peak, mult in (("f32", PEAK["f32"], 1), ("split6", PEAK["bf16"], 6), ("split3", PEAK["bf16"], 3)):
         roof = 0.0
         for (M, N, K) in shapes:
@@ -212,11 +218,27 @@ def grouped_section(torch, mm, reps=10):
             arr, cnt, mid, v, s, None, mm._stream(None))), reps, 2)
         info = plan.info()
         plan.close()
+        torch.cuda.synchronize()
+        # binary64 residual probe of every result, and the oracle's normwise
+        # error on a seeded sample of the problems
+        r2z2 = torch.empty((len(shapes), 2), dtype=torch.float64, device="cuda")
+        for i, (A, B, C) in enumerate(zip(As, Bs, Cs)):
+            mm.residual_f64(A, B, C, x_all[:B.shape[1]], out=r2z2[i], workspace=rws)
+        rr = r2z2.cpu().numpy()
+        rel = np.sqrt(rr[:, 0] / np.maximum(rr[:, 1], 1e-300))
+        errs = []
+        for i in sample:
+            M, N, K = shapes[i]
+            A, B = I.pair("uniform_f32", M, N, K, seed=(0, i))
+            errs.append(oracle.normwise_rel(Cs[i].cpu().numpy().astype(np.float64), oracle.gemm(A, B)))
         out[method] = {"variant": v, "schedule": s, "tiles": info["tiles"], "grid": info["grid"],
                        "graph_ms": ev, "eager_ms": eager[1],
                        "tflops_useful": flop / (ev * 1e-3) / 1e12, "roofline_ms": roof * 1e3,
-                       "frac_of_roofline": roof * 1e3 / ev}
-        log(f"  grouped {method}: {ev:.3f} ms graph, {eager[1]:.3f} ms eager, {out[method]['tflops_useful']:.1f} TFLOP/s")
+                       "frac_of_roofline": roof * 1e3 / ev,
+                       "freivalds_rel_residual_all": {"median": float(np.median(rel)), "max": float(rel.max())},
+                       "normwise_err_vs_oracle_sample": {"problems": len(errs), "max": float(max(errs))}}
+        log(f"  grouped {method}: {ev:.3f} ms graph, {eager[1]:.3f} ms eager, {out[method]['tflops_useful']:.1f} TFLOP/s, "
+            f"residual max {rel.max():.2e}, sampled error max {max(errs):.2e}")
     return out
 
 
