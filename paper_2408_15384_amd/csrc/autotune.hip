@@ -64,9 +64,9 @@ struct Candidate {
 
 const Candidate kF64Cand[] = {{4, 256, 128, 65.4, false}, {3, 128, 64, 56.3, false}, {6, 64, 64, 60.8, false}};
 const Candidate kF32Cand[] = {{2, 256, 128, 132.2, false}, {3, 128, 128, 122.4, false}, {6, 64, 64, 107.4, false}};
-const Candidate kSplit3Unfused[] = {{9, 256, 128, 330.0, true}, {6, 128, 128, 277.0, true}, {8, 64, 64, 217.0, true}};
+const Candidate kSplit3Unfused[] = {{14, 256, 128, 335.3, true}, {6, 128, 128, 277.0, true}, {8, 64, 64, 217.0, true}};
 const Candidate kSplit6Unfused[] = {{9, 256, 128, 203.7, true}, {6, 128, 128, 182.9, true}, {8, 64, 64, 120.9, true}};
-const Candidate kSplit3Cand[] = {{9, 256, 128, 330.0, true},  {6, 128, 128, 277.0, true},  {8, 64, 64, 217.0, true},
+const Candidate kSplit3Cand[] = {{14, 256, 128, 335.3, true}, {6, 128, 128, 277.0, true},  {8, 64, 64, 217.0, true},
                                  {10, 64, 64, 193.6, false},  {11, 128, 64, 234.7, false}, {12, 128, 128, 202.1, false}};
 const Candidate kSplit6Cand[] = {{9, 256, 128, 203.7, true},  {6, 128, 128, 182.9, true},  {8, 64, 64, 120.9, true},
                                  {10, 64, 64, 127.8, false},  {11, 128, 64, 147.1, false}, {12, 128, 128, 153.3, false}};

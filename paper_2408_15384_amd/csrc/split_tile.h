@@ -264,7 +264,13 @@ struct SplitTileDirect {
     static constexpr bool FUSED = false;
     using Terms = SplitTerms<NPROD>;
     static constexpr int NP = Terms::NP;
-    static constexpr int BM = BM_, BN = BN_, BK = 32, WM = WM_, WN = WN_, STAGES = STAGES_;
+    static constexpr int BM = BM_, BN = BN_, BK = 32, WM = WM_, WN = WN_;
+    // The ring holds STAGES_ buffers when they fit in 152 KiB of LDS (room is
+    // left for the grouped kernel's owner table), else as many as fit: a
+    // variant asks for a depth, and the 3-plane method may get a shallower one.
+    static constexpr int STAGE_BYTES = NP * (BM + BN) * BK * 2;
+    static constexpr int LDS_CAP = 152 * 1024;
+    static constexpr int STAGES = STAGES_ * STAGE_BYTES <= LDS_CAP ? STAGES_ : LDS_CAP / STAGE_BYTES;
     static constexpr int NWN = BN / WN;
     static constexpr int NWAVES = (BM / WM) * (BN / WN);
     static constexpr int NT = NWAVES * 64;

@@ -35,7 +35,9 @@
 // prefetch, or 10 + b: a ring of b LDS buffers fed by direct global-to-LDS
 // loads (BK 32) -- all three read bfloat16 planes made by a split pass -- or
 // 20: the fused tile, which reads the FP32 operands and splits them on the
-// way into LDS (BK 32, no plane pass, no workspace).
+// way into LDS (BK 32, no plane pass, no workspace).  A direct ring deeper
+// than LDS holds for the method's planes is made shallower (variant 14 is a
+// 3-buffer ring with 2 planes, a 2-buffer one with 3).
 #define MM_SPLIT_VARIANTS(X)          \
     X(0, 128, 128, 32, 64, 64, 1)     \
     X(1, 64, 64, 32, 32, 32, 1)       \
@@ -50,4 +52,5 @@
     X(10, 64, 64, 32, 32, 32, 20)     \
     X(11, 128, 64, 32, 64, 32, 20)    \
     X(12, 128, 128, 32, 64, 32, 20)   \
-    X(13, 128, 128, 32, 64, 64, 20)
+    X(13, 128, 128, 32, 64, 64, 20)   \
+    X(14, 256, 128, 32, 64, 64, 13)
