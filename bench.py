@@ -298,7 +298,7 @@ class ServingWorkload:
         return out
 
 
-def serving_section(torch, mm, wl=None, slots=4, max_batch=64, budget=64 << 30, variants=None, check=16):
+def serving_section(torch, mm, wl=None, slots=8, max_batch=64, budget=64 << 30, variants=None, check=16):
     import oracle
     if wl is None:
         wl = ServingWorkload(torch, mm)

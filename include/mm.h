@@ -335,7 +335,7 @@ typedef struct mm_server mm_server;
 
 typedef struct mm_serve_config {
     uint64_t budget_bytes;   /* admission budget: bytes of operands, results and split planes in flight */
-    int32_t slots;           /* concurrent launch slots (one HIP stream each), 1..8 */
+    int32_t slots;           /* concurrent launch slots (one HIP stream each), 1..16 */
     int32_t max_batch;       /* most requests packed into one grouped launch, 1..4096 */
     int32_t queue_capacity;  /* most requests waiting for admission; submit beyond it is MM_E_BUSY */
     int32_t device;          /* HIP device ordinal */

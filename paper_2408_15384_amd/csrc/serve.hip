@@ -288,7 +288,7 @@ extern "C" {
 mm_status mm_serve_create(const mm_serve_config *cfg, mm_server **out) {
     try {
         if (!cfg || !out) return fail(MM_E_INVAL, "NULL argument");
-        if (cfg->slots < 1 || cfg->slots > 8) return fail(MM_E_INVAL, "slots must be 1..8");
+        if (cfg->slots < 1 || cfg->slots > 16) return fail(MM_E_INVAL, "slots must be 1..16");
         if (cfg->max_batch < 1 || cfg->max_batch > 4096) return fail(MM_E_INVAL, "max_batch must be 1..4096");
         if (cfg->queue_capacity < 1) return fail(MM_E_INVAL, "queue_capacity must be positive");
         if (cfg->budget_bytes == 0) return fail(MM_E_INVAL, "budget_bytes must be positive");

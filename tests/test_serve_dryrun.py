@@ -174,3 +174,5 @@ def test_invalid_requests_rejected():
         srv.close()
     with pytest.raises(api.MMError):
         api.Server(budget_bytes=1 << 30, slots=0)
+    with pytest.raises(api.MMError):
+        api.Server(budget_bytes=1 << 30, slots=17)
