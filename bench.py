@@ -52,19 +52,33 @@ from paper_2408_15384_amd import inputs as I  # noqa: E402
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}   # dense TFLOP/s, MI355X datasheet
 HBM_TBS = 8.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_f64_8192.txt")
-KERNEL_SOURCES = ["paper_2408_15384_amd/csrc/gemm_tile.h", "paper_2408_15384_amd/csrc/gptr.h", "paper_2408_15384_amd/csrc/gemm_mfma.hip",
-                  "paper_2408_15384_amd/csrc/variants.h"]
+# What the headline kernel is compiled from: the tile bodies, the kernel
+# wrapper, the compile flags, and (added in kernel_source_hash) the variant's
+# own entry of the binary64 table.
+KERNEL_SOURCES = ["paper_2408_15384_amd/csrc/gemm_tile.h", "paper_2408_15384_amd/csrc/gptr.h",
+                  "paper_2408_15384_amd/csrc/gemm_mfma.hip", "paper_2408_15384_amd/build.py"]
+VARIANTS_FILE = "paper_2408_15384_amd/csrc/variants.h"
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
+def f64_variant_entry(variant: int) -> str:
+    """The X(variant, ...) entry of the binary64 variant table."""
+    import re
+    text = open(os.path.join(ROOT, VARIANTS_FILE)).read()
+    table = text[text.index("#define MM_F64_VARIANTS"):text.index("#define MM_F32_VARIANTS")]
+    m = re.search(r"X\(\s*%d\s*,[^)]*\)" % variant, table)
+    return m.group(0) if m else ""
+
+
+def kernel_source_hash(variant: int = 4) -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
+    h.update(f64_variant_entry(variant).encode())
     return h.hexdigest()[:16]
 
 
@@ -79,7 +93,7 @@ def read_traffic(variant):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_source_sha") != kernel_source_hash():
+    if vals.get("kernel_source_sha") != kernel_source_hash(variant):
         return None
     if vals.get("tile_variant") != str(variant):
         return None
