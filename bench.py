@@ -23,6 +23,7 @@ Also reported in the same line (context, not the headline):
     the device, a 64 GiB admission budget; p50/p99 latency and throughput,
     the residual probe of every result;
 
+  * peak: the MFMA-only throughput of each dtype on this GPU (the ceiling);
   * strassen: one Strassen-Winograd level on the binary64 product at 8192;
   * shard: one GPU's share (1024 rows) of a row-sharded 8192 product;
   * layouts: transposed operands (NN, NT, TN, TT) at 8192;
@@ -30,7 +31,7 @@ Also reported in the same line (context, not the headline):
     against the oracle on one and on all host cores.
 
 Usage: python bench.py [--gpus 1] [--steps 15] [--warmup 3]
-                       [--sections precision,grouped,serving,strassen,shard,layouts,paper|none]
+                       [--sections peak,precision,grouped,serving,strassen,shard,layouts,paper|none]
                        [--no-cpu-baseline]
 """
 from __future__ import annotations
@@ -52,11 +53,11 @@ from paper_2408_15384_amd import inputs as I  # noqa: E402
 PEAK = {"f64": 78.6, "f32": 157.3, "bf16": 2516.6}   # dense TFLOP/s, MI355X datasheet
 HBM_TBS = 8.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gemm_f64_8192.txt")
-# What the headline kernel is compiled from: the tile bodies, the kernel
-# wrapper, the compile flags, and (added in kernel_source_hash) the variant's
-# own entry of the binary64 table.
+# What the headline kernel is compiled from: the tile bodies and the kernel
+# wrapper, plus (added in kernel_source_hash) the compile flags and the
+# variant's own entry of the binary64 table.
 KERNEL_SOURCES = ["paper_2408_15384_amd/csrc/gemm_tile.h", "paper_2408_15384_amd/csrc/gptr.h",
-                  "paper_2408_15384_amd/csrc/gemm_mfma.hip", "paper_2408_15384_amd/build.py"]
+                  "paper_2408_15384_amd/csrc/gemm_mfma.hip"]
 VARIANTS_FILE = "paper_2408_15384_amd/csrc/variants.h"
 
 
@@ -78,6 +79,8 @@ def kernel_source_hash(variant: int = 4) -> str:
     for p in KERNEL_SOURCES:
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
+    from paper_2408_15384_amd import build as B
+    h.update(repr([B.ARCH, *B.COMMON[:-2], *B.DEVICE_FLAGS]).encode())   # flags, less the include path
     h.update(f64_variant_entry(variant).encode())
     return h.hexdigest()[:16]
 
@@ -412,6 +415,50 @@ def strassen_section(torch, mm, n=8192, reps=5):
     return out
 
 
+def peak_section(torch, achieved_f64=None):
+    """MFMA-only throughput per dtype (libmm_peak.so, include/mm_peak.h): the
+    ceiling the products' fractions of the datasheet peaks are read against.
+    The best of 8, 16 or 32 independent accumulator chains per wave and 2, 4,
+    8 or 16 four-wave workgroups per CU, each launch ~5-20 ms."""
+    import ctypes
+    from paper_2408_15384_amd import build as B
+    lib = ctypes.CDLL(B.PEAK_LIB)
+    fn = lib.mm_peak_mfma
+    fn.restype = ctypes.c_int32
+    fn.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    out_buf = torch.empty(16 * cus * 256, dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    res = {}
+    # total MFMAs per launch held fixed per dtype: per_cu * cus * 4 waves * iters * chains
+    for name, code, flop, mfmas_per_wave in (("f64", 0, 2048, 48000 * 8 // 2), ("f32", 1, 2048, 96000 * 8 // 2),
+                                             ("bf16", 2, 16384, 192000 * 8 // 2)):
+        best = None
+        for chains in (8, 16, 32):
+            for per_cu in (2, 4, 8, 16):
+                blocks = per_cu * cus
+                iters = max(1, mfmas_per_wave // (per_cu * chains))
+                if fn(code, chains, blocks, max(1, iters // 10), out_buf.data_ptr(), stream) != 0:
+                    raise RuntimeError("mm_peak_mfma failed")
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                if fn(code, chains, blocks, iters, out_buf.data_ptr(), stream) != 0:
+                    raise RuntimeError("mm_peak_mfma failed")
+                e1.record()
+                e1.synchronize()
+                t = e0.elapsed_time(e1) * 1e-3
+                tf = blocks * 4 * iters * chains * flop / t / 1e12
+                if best is None or tf > best["tflops"]:
+                    best = {"tflops": tf, "chains": chains, "workgroups_per_cu": per_cu}
+        best["frac_of_datasheet"] = best["tflops"] / PEAK[name]
+        res[name] = best
+        log(f"  MFMA-only {name}: {best['tflops']:.1f} TFLOP/s ({best['frac_of_datasheet']:.1%} of {PEAK[name]}), "
+            f"{best['chains']} chains, {best['workgroups_per_cu']} workgroups/CU")
+    if achieved_f64:
+        res["headline_frac_of_f64_ceiling"] = achieved_f64 / res["f64"]["tflops"]
+    return res
+
+
 def shard_section(torch, mm, n=8192, parts=8, reps=15):
     """One GPU's share of a row-sharded binary64 product at n: A's and C's rows
     [0, n/parts) times all of B.  Rows of C do not depend on how the rows are
@@ -529,8 +576,8 @@ def main():
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--sections", default="precision,grouped,serving,strassen,shard,layouts,paper",
-                    help="comma list of sections to run after the headline (precision, grouped, serving, strassen, shard, layouts, "
+    ap.add_argument("--sections", default="peak,precision,grouped,serving,strassen,shard,layouts,paper",
+                    help="comma list of sections to run after the headline (peak, precision, grouped, serving, strassen, shard, layouts, "
                          "paper; "
                          "or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -587,6 +634,9 @@ def main():
     del dA, dB, dC
     torch.cuda.empty_cache()
     sections = [x for x in args.sections.split(",") if x and x != "none"]
+    if "peak" in sections:
+        log("peak: MFMA-only throughput per dtype")
+        line["mfma_peak"] = peak_section(torch, achieved)
     if "precision" in sections:
         log("precision: FP32 vs split-bf16 at N=8192")
         line["precision"] = precision_section(torch, mm, n, args.steps, args.warmup)

@@ -3,7 +3,8 @@
     python -m paper_2408_15384_amd.build
 
 Every source under csrc/ is compiled by hipcc to an object in _build/ (in
-parallel), then linked into paper_2408_15384_amd/libmm.so."""
+parallel), then linked into paper_2408_15384_amd/libmm.so.  The MFMA-only
+measurement aid peak/mfma_peak.hip becomes libmm_peak.so."""
 from __future__ import annotations
 
 import concurrent.futures as cf
@@ -43,7 +44,29 @@ def _compile(src: str) -> str:
     return obj
 
 
+PEAK_SRC = os.path.join(HERE, "peak", "mfma_peak.hip")
+PEAK_LIB = os.path.join(HERE, "libmm_peak.so")
+
+
+def build_peak(verbose: bool = True) -> str:
+    """The MFMA-only measurement aid (include/mm_peak.h) as its own library."""
+    tmp = PEAK_LIB + ".tmp"
+    # accumulators in VGPRs: otherwise the binary64 chains are copied between
+    # accumulation and vector registers on every iteration and the probe
+    # measures the copies
+    cmd = [hipcc(), *COMMON, *DEVICE_FLAGS, "-mllvm", "-amdgpu-mfma-vgpr-form=1", "-shared", "-o", tmp, PEAK_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PEAK_SRC}:\n{r.stderr}")
+    os.replace(tmp, PEAK_LIB)
+    if verbose:
+        print(f"built {PEAK_LIB}", file=sys.stderr)
+    return PEAK_LIB
+
+
 def build(verbose: bool = True) -> str:
+    """Build libmm.so (and the measurement aid libmm_peak.so)."""
+    build_peak(verbose)
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = min(len(srcs), max(1, min(16, os.cpu_count() or 1)))

@@ -14,8 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "mm.h")
 
 
-def declared_functions():
-    text = open(HEADER).read()
+def declared_functions(header=HEADER):
+    text = open(header).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(mm_[a-z0-9_]+)\s*\(", text)))
 
@@ -31,6 +31,23 @@ def test_every_declared_symbol_is_exported(lib):
     missing = [n for n in names if not hasattr(lib, n)]
     assert not missing, missing
     assert sorted(n for n, _, _ in api.EXPORTS) == names   # binding declares exactly the header
+
+
+def test_peak_library_exports_its_header():
+    # the MFMA-only measurement aid is a library of its own beside libmm
+    import torch  # noqa: F401  -- same HIP runtime binding order as libmm
+    from paper_2408_15384_amd import build as B
+    peak = ctypes.CDLL(B.PEAK_LIB)
+    names = declared_functions(os.path.join(ROOT, "include", "mm_peak.h"))
+    assert names == ["mm_peak_mfma"]
+    assert all(hasattr(peak, n) for n in names)
+    fn = peak.mm_peak_mfma
+    fn.restype = ctypes.c_int32
+    fn.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    assert fn(3, 8, 1, 1, 1024, None) == -1      # bad dtype: rejected before any launch
+    assert fn(0, 12, 1, 1, 1024, None) == -1     # unsupported chain count
+    assert fn(0, 8, 0, 1, 1024, None) == -1      # no blocks
+    assert fn(0, 8, 1, 1, None, None) == -1      # no output
 
 
 def test_status_strings(lib):

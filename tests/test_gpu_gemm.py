@@ -336,3 +336,21 @@ def test_f32_and_split_8192_rows(mm, kind):
             assert err <= 1e-6, (nprod, kind, err)
         else:
             assert err <= 1e-5, (nprod, kind, err)
+
+
+def test_peak_probe_runs(mm):
+    """The MFMA-only measurement aid launches for every dtype and writes its
+    output (it computes no product, so only completion is checked)."""
+    import ctypes
+    from paper_2408_15384_amd import build as B
+    lib = ctypes.CDLL(B.PEAK_LIB)
+    fn = lib.mm_peak_mfma
+    fn.restype = ctypes.c_int32
+    fn.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    out = torch.full((4 * 256,), float("nan"), dtype=torch.float32, device="cuda")
+    for dtype in (0, 1, 2):
+        for chains in (8, 16, 32):
+            out.fill_(float("nan"))
+            assert fn(dtype, chains, 4, 16, out.data_ptr(), torch.cuda.current_stream().cuda_stream) == 0
+            torch.cuda.synchronize()
+            assert torch.isfinite(out).all()
