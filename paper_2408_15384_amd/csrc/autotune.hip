@@ -62,9 +62,9 @@ struct Candidate {
     bool plane_pass;
 };
 
-const Candidate kF64Cand[] = {{4, 256, 128, 65.4, false}, {3, 128, 64, 56.3, false}, {6, 64, 64, 60.8, false},
+const Candidate kF64Cand[] = {{12, 256, 128, 67.5, false}, {3, 128, 64, 56.3, false}, {6, 64, 64, 60.8, false},
                               {9, 32, 32, 50.1, false}};
-const Candidate kF32Cand[] = {{2, 256, 128, 132.2, false}, {3, 128, 128, 122.4, false}, {6, 64, 64, 107.4, false},
+const Candidate kF32Cand[] = {{12, 256, 128, 136.0, false}, {3, 128, 128, 122.4, false}, {6, 64, 64, 107.4, false},
                               {10, 32, 32, 69.0, false}};
 const Candidate kSplit3Unfused[] = {{14, 256, 128, 335.3, true}, {6, 128, 128, 277.0, true}, {8, 64, 64, 217.0, true}};
 const Candidate kSplit6Unfused[] = {{9, 256, 128, 203.7, true}, {6, 128, 128, 182.9, true}, {8, 64, 64, 120.9, true}};
