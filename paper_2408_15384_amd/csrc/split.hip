@@ -7,6 +7,7 @@
 //
 // Split GEMM: the tile in split_tile.h over the planes, one workgroup per tile.
 #include "mm_internal.h"
+#include "gemm_tile.h"   // tile_order
 #include "split_tile.h"
 #include "variants.h"
 
@@ -127,19 +128,6 @@ size_t split_workspace_bytes(int64_t M, int64_t N, int64_t K, int nprod) {
     return split_b_offset_bytes(M, K, nprod) + (size_t)np * N * split_padded_k(K) * 2;
 }
 
-__device__ void tile_order_split(int64_t bid, int64_t tiles_m, int64_t tiles_n, int64_t *tm, int64_t *tn) {
-    const int64_t total = tiles_m * tiles_n;
-    int64_t b = bid;
-    if (total % 8 == 0) b = (bid % 8) * (total / 8) + bid / 8;
-    const int group_m = 8;
-    const int64_t per_group = (int64_t)group_m * tiles_n;
-    const int64_t g = b / per_group;
-    const int64_t first_m = g * group_m;
-    const int64_t gsize = (tiles_m - first_m) < group_m ? (tiles_m - first_m) : group_m;
-    const int64_t in = b % per_group;
-    *tm = first_m + in % gsize;
-    *tn = in / gsize;
-}
 
 template <typename ST>
 __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void split_gemm_kernel(const uint16_t *__restrict__ Ap, int64_t pa_stride,
@@ -148,7 +136,7 @@ __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void split_gemm_
                                                             int64_t K, int64_t tiles_m, int64_t tiles_n, int vec_ok) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
     int64_t tm, tn;
-    tile_order_split(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
+    tile_order(blockIdx.x, tiles_m, tiles_n, 8, &tm, &tn);
     ST::run(Ap, pa_stride, Bt, pb_stride, C, ldc, c_is_f64, M, N, K, tm, tn, vec_ok != 0, smem);
 }
 
@@ -158,7 +146,7 @@ __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void split_fused
     int c_is_f64, int64_t M, int64_t N, int64_t K, int64_t tiles_m, int64_t tiles_n) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
     int64_t tm, tn;
-    tile_order_split(blockIdx.x, tiles_m, tiles_n, &tm, &tn);
+    tile_order(blockIdx.x, tiles_m, tiles_n, 8, &tm, &tn);
     ST::run_fused(A, lda, B, ldb, C, ldc, c_is_f64, M, N, K, tm, tn, smem);
 }
 
