@@ -256,18 +256,20 @@ mm_status mm_grouped_plan_destroy(mm_grouped_plan *plan);
 mm_status mm_grouped_plan_launch(mm_grouped_plan *plan, void *stream);
 
 /* Tile configuration the plan chose (autotuned or default), its schedule, its
- * tile count, the workgroups of its persistent grid and whether it replays a
- * graph.  Every output is nullable. */
+ * tile count, the workgroups of its grid (persistent grid, or one per tile for
+ * schedule 3) and whether it replays a graph.  Every output is nullable. */
 mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out, int32_t *schedule_out,
                                int64_t *tiles_out, int32_t *grid_out, int32_t *uses_graph_out);
 
 /*
  * mm_gemm_grouped_config -- mm_gemm_grouped with an explicit tile variant and
  * schedule instead of the autotuned choice.  schedule: 0 = problems in the
- * given order, workgroups take tiles by a fixed stride; 1 = heaviest problems
- * (largest M*N*K) first, fixed stride; 2 = heaviest first, workgroups pull
- * tiles from a device work counter.  An existing plan must have been built
- * with the same variant and schedule.
+ * given order, a persistent grid takes tiles by a fixed stride; 1 = heaviest
+ * problems (largest M*N*K) first, fixed stride; 2 = heaviest first, the
+ * persistent grid pulls tiles from a device work counter; 3 = heaviest first,
+ * one workgroup per tile dispatched in tile order by the hardware.  Every
+ * schedule gives the same bits.  An existing plan must have been built with
+ * the same variant and schedule.
  */
 mm_status mm_gemm_grouped_config(const mm_problem *probs, int32_t count, mm_method method,
                                  int32_t variant, int32_t schedule,

@@ -242,7 +242,7 @@ mm_status mm_grouped_autotune(const mm_problem *probs, int32_t count, mm_method 
         double best_ms = 0;
         mm_status status = MM_OK;
         for (int v = 0; v < nv && status == MM_OK; ++v) {
-            for (int sch = 0; sch <= 2 && status == MM_OK; ++sch) {
+            for (int sch = 0; sch <= 3 && status == MM_OK; ++sch) {
                 mm_grouped_plan *plan = nullptr;
                 std::vector<float> times;
                 for (int r = 0; r < warmup + reps; ++r) {
@@ -370,7 +370,7 @@ mm_status mm_autotune_load(const char *path) {
             const int k0 = (int)v[0], variant = (int)v[4], schedule = (int)v[6];
             const int method = k0 >= 100 ? k0 - 100 : k0;
             if (method < 0 || method > 3 || variant < 0 || variant >= mm_variant_count((mm_method)method) ||
-                schedule < 0 || schedule > 2)
+                schedule < 0 || schedule > 3)
                 return fail(MM_E_INVAL, "entry names an unknown method, variant or schedule");
             fresh[Key(k0, (int)v[1], (int)v[2], (int)v[3])] = Entry{variant, v[5], schedule};
             p = close + 1;

@@ -88,51 +88,83 @@ __device__ __forceinline__ int64_t next_tile(int64_t cur, const int *counter, in
     return uniform(*slot);
 }
 
-// Two waves per SIMD are asked of 4-wave tiles whose LDS lets two workgroups
-// share a CU; otherwise one.
+// One tile of a grouped launch: decode the owner's descriptor and run the
+// single-problem tile body on it.
 template <typename TG, typename T>
-__global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 && TG::LDS_ELEMS * sizeof(T) <= 76 * 1024 ? 2 : 1)) void grouped_gemm_kernel(
-    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter) {
-    __shared__ __attribute__((aligned(16))) T smem[TG::LDS_ELEMS];
-    __shared__ int32_t s_begin[kOwnerCap];
-    __shared__ int64_t slot;
-    const bool cached = stage_begins<kOwnerCap>(descs, count, total_tiles, s_begin);
-    for (int64_t t = blockIdx.x; t < total_tiles;) {
-        const int ticket = draw_ticket(counter);
-        const GroupedDesc &d = descs[uniform(find_owner(descs, s_begin, cached, count, t))];
-        const int64_t local = t - d.tile_begin;
-        const int64_t tm = uniform(local / d.tiles_n), tn = uniform(local % d.tiles_n);
-        const bool vec_ok = (d.lda % TG::VEC == 0) && (d.ldb % TG::VEC == 0) && ((uintptr_t)d.A % 16 == 0) &&
-                            ((uintptr_t)d.B % 16 == 0);
-        TG::run((const T *)d.A, d.lda, (const T *)d.B, d.ldb, (T *)d.C, d.ldc, d.M, d.N, d.K, tm, tn, vec_ok, smem);
-        __syncthreads();
-        t = next_tile(t, counter, ticket, &slot);
-    }
+__device__ __forceinline__ void grouped_dense_tile(const GroupedDesc *__restrict__ descs, int own, int64_t t, T *smem) {
+    const GroupedDesc &d = descs[own];
+    const int64_t local = t - d.tile_begin;
+    const int64_t tm = uniform(local / d.tiles_n), tn = uniform(local % d.tiles_n);
+    const bool vec_ok = (d.lda % TG::VEC == 0) && (d.ldb % TG::VEC == 0) && ((uintptr_t)d.A % 16 == 0) &&
+                        ((uintptr_t)d.B % 16 == 0);
+    TG::run((const T *)d.A, d.lda, (const T *)d.B, d.ldb, (T *)d.C, d.ldc, d.M, d.N, d.K, tm, tn, vec_ok, smem);
 }
 
 template <typename ST>
-__global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void grouped_split_gemm_kernel(const GroupedDesc *__restrict__ descs, int count,
-                                                                    int64_t total_tiles, int *counter) {
-    __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
-    __shared__ int32_t s_begin[kOwnerCap];
-    __shared__ int64_t slot;
-    const bool cached = stage_begins<kOwnerCap>(descs, count, total_tiles, s_begin);
-    for (int64_t t = blockIdx.x; t < total_tiles;) {
-        const int ticket = draw_ticket(counter);
-        const GroupedDesc &d = descs[uniform(find_owner(descs, s_begin, cached, count, t))];
-        const int64_t local = t - d.tile_begin;
-        const int64_t tm = uniform(local / d.tiles_n), tn = uniform(local % d.tiles_n);
-        if constexpr (ST::FUSED) {
-            // descriptors hold the FP32 operands themselves
-            ST::run_fused((const float *)d.A, d.lda, (const float *)d.B, d.ldb, d.C, d.ldc, 0, d.M, d.N, d.K, tm, tn,
-                          smem);
-        } else {
-            const bool vec_ok = (d.K % 8 == 0) && ((uintptr_t)d.A % 16 == 0) && ((uintptr_t)d.B % 16 == 0);
-            ST::run((const uint16_t *)d.A, d.M * d.K, (const uint16_t *)d.B, d.N * d.K, d.C, d.ldc, 0, d.M, d.N, d.K,
-                    tm, tn, vec_ok, smem);
+__device__ __forceinline__ void grouped_split_tile(const GroupedDesc *__restrict__ descs, int own, int64_t t,
+                                                   uint16_t *smem) {
+    const GroupedDesc &d = descs[own];
+    const int64_t local = t - d.tile_begin;
+    const int64_t tm = uniform(local / d.tiles_n), tn = uniform(local % d.tiles_n);
+    if constexpr (ST::FUSED) {
+        // descriptors hold the FP32 operands themselves
+        ST::run_fused((const float *)d.A, d.lda, (const float *)d.B, d.ldb, d.C, d.ldc, 0, d.M, d.N, d.K, tm, tn, smem);
+    } else {
+        const bool vec_ok = (d.K % 8 == 0) && ((uintptr_t)d.A % 16 == 0) && ((uintptr_t)d.B % 16 == 0);
+        ST::run((const uint16_t *)d.A, d.M * d.K, (const uint16_t *)d.B, d.N * d.K, d.C, d.ldc, 0, d.M, d.N, d.K, tm,
+                tn, vec_ok, smem);
+    }
+}
+
+// Two forms of each grouped kernel.  PERSISTENT: a grid the chip holds at
+// once loops over the tiles (fixed stride, or tickets from the work counter).
+// Otherwise one workgroup per tile, in tile order, dispatched by the
+// hardware: no loop, so the tile body keeps the registers of the single-problem
+// kernel (the loop over tiles costs registers: the compiler hoists the per-
+// thread index arithmetic of the tile body out of it).
+// Two waves per SIMD are asked of 4-wave tiles whose LDS lets two workgroups
+// share a CU; otherwise one.
+template <typename TG, typename T, bool PERSISTENT>
+__global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 && TG::LDS_ELEMS * sizeof(T) <= 76 * 1024 ? 2 : 1)) void grouped_gemm_kernel(
+    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter) {
+    __shared__ __attribute__((aligned(16))) T smem[TG::LDS_ELEMS];
+    if constexpr (PERSISTENT) {
+        __shared__ int32_t s_begin[kOwnerCap];
+        __shared__ int64_t slot;
+        const bool cached = stage_begins<kOwnerCap>(descs, count, total_tiles, s_begin);
+        for (int64_t t = blockIdx.x; t < total_tiles;) {
+            const int ticket = draw_ticket(counter);
+            grouped_dense_tile<TG, T>(descs, uniform(find_owner(descs, s_begin, cached, count, t)), t, smem);
+            __syncthreads();
+            t = next_tile(t, counter, ticket, &slot);
         }
-        __syncthreads();
-        t = next_tile(t, counter, ticket, &slot);
+    } else {
+        const int64_t t = blockIdx.x;
+        if (t < total_tiles)
+            grouped_dense_tile<TG, T>(descs, uniform(find_owner(descs, (const int32_t *)nullptr, false, count, t)), t,
+                                      smem);
+    }
+}
+
+template <typename ST, bool PERSISTENT>
+__global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void grouped_split_gemm_kernel(
+    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter) {
+    __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
+    if constexpr (PERSISTENT) {
+        __shared__ int32_t s_begin[kOwnerCap];
+        __shared__ int64_t slot;
+        const bool cached = stage_begins<kOwnerCap>(descs, count, total_tiles, s_begin);
+        for (int64_t t = blockIdx.x; t < total_tiles;) {
+            const int ticket = draw_ticket(counter);
+            grouped_split_tile<ST>(descs, uniform(find_owner(descs, s_begin, cached, count, t)), t, smem);
+            __syncthreads();
+            t = next_tile(t, counter, ticket, &slot);
+        }
+    } else {
+        const int64_t t = blockIdx.x;
+        if (t < total_tiles)
+            grouped_split_tile<ST>(descs, uniform(find_owner(descs, (const int32_t *)nullptr, false, count, t)), t,
+                                   smem);
     }
 }
 
@@ -185,16 +217,16 @@ struct KernelInfo {
     int nt = 0, bm = 0, bn = 0;
 };
 
-static KernelInfo kernel_for(mm_method method, int variant) {
+static KernelInfo kernel_for(mm_method method, int variant, bool persistent = true) {
     KernelInfo k;
 #define MM_GK_F64(id, bm_, bn_, bk, wm, wn, st) \
-    case id: k.fn = (KernelPtr)&grouped_gemm_kernel<TileSel<double, bm_, bn_, bk, wm, wn, st>::type, double>; k.nt = TileSel<double, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
+    case id: k.fn = persistent ? (KernelPtr)&grouped_gemm_kernel<TileSel<double, bm_, bn_, bk, wm, wn, st>::type, double, true> : (KernelPtr)&grouped_gemm_kernel<TileSel<double, bm_, bn_, bk, wm, wn, st>::type, double, false>; k.nt = TileSel<double, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
 #define MM_GK_F32(id, bm_, bn_, bk, wm, wn, st) \
-    case id: k.fn = (KernelPtr)&grouped_gemm_kernel<TileSel<float, bm_, bn_, bk, wm, wn, st>::type, float>; k.nt = TileSel<float, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
+    case id: k.fn = persistent ? (KernelPtr)&grouped_gemm_kernel<TileSel<float, bm_, bn_, bk, wm, wn, st>::type, float, true> : (KernelPtr)&grouped_gemm_kernel<TileSel<float, bm_, bn_, bk, wm, wn, st>::type, float, false>; k.nt = TileSel<float, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
 #define MM_GK_S3(id, bm_, bn_, bk, wm, wn, st) \
-    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type>; k.nt = SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
+    case id: k.fn = persistent ? (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type, true> : (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type, false>; k.nt = SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
 #define MM_GK_S6(id, bm_, bn_, bk, wm, wn, st) \
-    case id: k.fn = (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type>; k.nt = SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
+    case id: k.fn = persistent ? (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type, true> : (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type, false>; k.nt = SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
     switch (method) {
         case MM_F64: switch (variant) { MM_F64_VARIANTS(MM_GK_F64) default: break; } break;
         case MM_F32: switch (variant) { MM_F32_VARIANTS(MM_GK_F32) default: break; } break;
@@ -290,8 +322,10 @@ void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_met
     L->ws_bytes = off;
 }
 
-// Launch order of the problems.  0: as given; 1 and 2: largest K*M*N first
-// (heaviest tiles start first); 2 additionally pulls tiles from a work counter.
+// Launch order of the problems.  0: as given; 1, 2 and 3: largest K*M*N first
+// (heaviest tiles start first).  How tiles reach workgroups: 0 and 1 a
+// persistent grid by fixed stride, 2 a persistent grid pulling from a work
+// counter, 3 one workgroup per tile dispatched in tile order by the hardware.
 std::vector<int> schedule_order(const mm_problem *probs, int count, int schedule) {
     std::vector<int> order(count);
     std::iota(order.begin(), order.end(), 0);
@@ -306,17 +340,22 @@ std::vector<int> schedule_order(const mm_problem *probs, int count, int schedule
 }
 
 // Enqueue the whole grouped sequence for descriptors already on the device.
-hipError_t grouped_enqueue(mm_method method, int variant, const GroupedDesc *d_descs, int ndesc, int64_t total_tiles,
-                          const SplitJob *d_jobs, int njobs, int64_t split_tiles, int *d_counter, hipStream_t st) {
+// d_counter (schedule 2 only) is the work counter; persistent == false runs
+// one workgroup per tile (schedule 3).
+hipError_t grouped_enqueue(mm_method method, int variant, bool persistent, const GroupedDesc *d_descs, int ndesc,
+                          int64_t total_tiles, const SplitJob *d_jobs, int njobs, int64_t split_tiles, int *d_counter,
+                          hipStream_t st) {
     if (ndesc == 0) return hipSuccess;
-    const KernelInfo k = kernel_for(method, variant);
+    const KernelInfo k = kernel_for(method, variant, persistent);
     if (!k.fn) return hipErrorInvalidValue;
+    if (!persistent && total_tiles > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     if (njobs > 0 && split_tiles > 0) {
         int64_t g = split_tiles < 4096 ? split_tiles : 4096;
         hipLaunchKernelGGL(grouped_split_kernel, dim3((unsigned)g), dim3(256), 0, st, d_jobs, njobs, split_tiles);
     }
+    if (!persistent) d_counter = nullptr;
     if (d_counter) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, d_counter);
-    int64_t grid = persistent_grid(method, variant, k.fn, k.nt);
+    int64_t grid = persistent ? persistent_grid(method, variant, k.fn, k.nt) : total_tiles;
     if (grid > total_tiles) grid = total_tiles;
     void *args[] = {(void *)&d_descs, (void *)&ndesc, (void *)&total_tiles, (void *)&d_counter};
     return hipLaunchKernel(k.fn, dim3((unsigned)grid), dim3(k.nt), args, 0, st);
@@ -411,7 +450,7 @@ static mm_status create_plan(const mm_problem *probs, int32_t count, mm_method m
     if (e == hipSuccess && nd) {
         e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = grouped_enqueue(method, variant, p->d_descs, (int)nd, p->layout.total_tiles, p->d_jobs, (int)nj,
+            hipError_t le = grouped_enqueue(method, variant, schedule != 3, p->d_descs, (int)nd, p->layout.total_tiles, p->d_jobs, (int)nj,
                                     p->layout.split_tiles, p->d_counter, p->capture_stream);
             hipError_t ce = hipStreamEndCapture(p->capture_stream, &p->graph);
             e = le != hipSuccess ? le : ce;
@@ -483,7 +522,7 @@ static mm_status run_once(const mm_problem *probs, int32_t count, mm_method meth
     // the host vectors must outlive the copies
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess)
-        e = grouped_enqueue(method, variant, d_descs, (int)nd, L.total_tiles, d_jobs, (int)L.jobs.size(), L.split_tiles,
+        e = grouped_enqueue(method, variant, schedule != 3, d_descs, (int)nd, L.total_tiles, d_jobs, (int)L.jobs.size(), L.split_tiles,
                     d_counter, st);
     hipError_t e2 = hipFreeAsync(buf, st);
     if (e == hipSuccess) e = e2;
@@ -551,8 +590,9 @@ mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out
     if (tiles_out) *tiles_out = plan->layout.total_tiles;
     if (grid_out) {
         const KernelInfo k = kernel_for(plan->method, plan->variant);
-        int64_t g = persistent_grid(plan->method, plan->variant, k.fn, k.nt);
-        *grid_out = (int32_t)(g < plan->layout.total_tiles ? g : plan->layout.total_tiles);
+        int64_t g = plan->schedule == 3 ? plan->layout.total_tiles : persistent_grid(plan->method, plan->variant, k.fn, k.nt);
+        if (g > plan->layout.total_tiles) g = plan->layout.total_tiles;
+        *grid_out = (int32_t)(g < 0x7fffffffLL ? g : 0x7fffffffLL);
     }
     if (uses_graph_out) *uses_graph_out = plan->exec != nullptr;
     return MM_OK;
@@ -565,7 +605,7 @@ mm_status mm_gemm_grouped_config(const mm_problem *probs, int32_t count, mm_meth
         mm_status s = validate(probs, count, method);
         if (s != MM_OK) return s;
         if (variant < 0 || variant >= mm_variant_count(method)) return fail(MM_E_INVAL, "no such variant");
-        if (schedule < 0 || schedule > 2) return fail(MM_E_INVAL, "schedule must be 0, 1 or 2");
+        if (schedule < 0 || schedule > 3) return fail(MM_E_INVAL, "schedule must be 0, 1, 2 or 3");
         hipStream_t st = (hipStream_t)stream;
         if (plan_inout && *plan_inout) {
             mm_grouped_plan *p = *plan_inout;

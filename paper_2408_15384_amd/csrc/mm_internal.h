@@ -143,7 +143,7 @@ void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_met
                   char *ws, Layout *L);
 // Enqueue [grouped split pass] -> [counter reset] -> grouped GEMM for
 // descriptors already in device memory.
-hipError_t grouped_enqueue(mm_method method, int variant, const GroupedDesc *d_descs, int ndesc, int64_t total_tiles,
+hipError_t grouped_enqueue(mm_method method, int variant, bool persistent, const GroupedDesc *d_descs, int ndesc, int64_t total_tiles,
                            const SplitJob *d_jobs, int njobs, int64_t split_tiles, int *d_counter, hipStream_t st);
 // Keep memory freed by hipFreeAsync in the device's default pool.
 void retain_default_pool();

@@ -211,7 +211,7 @@ static mm_status launch(mm_server *s, Slot &slot, const std::vector<uint64_t> &i
             std::memcpy(hj, L[g].jobs.data(), L[g].jobs.size() * sizeof(SplitJob));
             MM_HIP(hipMemcpyAsync(dj, hj, L[g].jobs.size() * sizeof(SplitJob), hipMemcpyHostToDevice, slot.stream));
         }
-        MM_HIP(grouped_enqueue(m, variant, dd, (int)L[g].descs.size(), L[g].total_tiles, dj, (int)L[g].jobs.size(),
+        MM_HIP(grouped_enqueue(m, variant, true, dd, (int)L[g].descs.size(), L[g].total_tiles, dj, (int)L[g].jobs.size(),
                                L[g].split_tiles, slot.d_counters + g, slot.stream));
     }
     MM_HIP(hipEventRecord(slot.done, slot.stream));

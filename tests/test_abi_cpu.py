@@ -71,6 +71,9 @@ def test_invalid_arguments_without_gpu(lib):
     assert lib.mm_gemm_grouped(probs, 1, api.MM_F64, None, None) == api.MM_E_INVAL
     assert b"problem 0" in lib.mm_last_error()
     assert lib.mm_gemm_grouped(probs, 0, api.MM_F64, None, None) == api.MM_OK
+    assert lib.mm_gemm_grouped_config(probs, 0, api.MM_F64, 0, 4, None, None) == api.MM_E_INVAL   # schedule 0..3
+    assert b"schedule" in lib.mm_last_error()
+    assert lib.mm_gemm_grouped_config(probs, 0, api.MM_F64, 0, 3, None, None) == api.MM_OK
 
 
 def test_variant_tables(lib):

@@ -78,7 +78,7 @@ def test_grouped_equals_single_every_schedule(mm, method):
     As, Bs, Cs, hostAB = make_batch(method, shapes, seed=2)
     variant = 1
     ref = singles(mm, method, variant, As, Bs)
-    for schedule in (0, 1, 2):
+    for schedule in (0, 1, 2, 3):
         for C in Cs:
             C.fill_(float("nan"))
         mm.gemm_grouped(method, As, Bs, Cs, variant=variant, schedule=schedule)
@@ -95,12 +95,13 @@ def test_grouped_every_split_variant(mm, method):
     As, Bs, Cs, hostAB = make_batch(method, shapes, seed=22)
     for variant in range(mm.variant_count(method)):
         ref = singles(mm, method, variant, As, Bs)
-        for C in Cs:
-            C.fill_(float("nan"))
-        mm.gemm_grouped(method, As, Bs, Cs, variant=variant, schedule=2)
-        torch.cuda.synchronize()
-        for i, C in enumerate(Cs):
-            assert np.array_equal(C.cpu().numpy(), ref[i]), f"variant {variant} problem {i}"
+        for schedule in (2, 3):
+            for C in Cs:
+                C.fill_(float("nan"))
+            mm.gemm_grouped(method, As, Bs, Cs, variant=variant, schedule=schedule)
+            torch.cuda.synchronize()
+            for i, C in enumerate(Cs):
+                assert np.array_equal(C.cpu().numpy(), ref[i]), f"variant {variant} schedule {schedule} problem {i}"
     check_oracle(method, hostAB, Cs, range(len(shapes)))
 
 
@@ -178,7 +179,7 @@ def test_autotuners(mm, tmp_path):
     shapes = ragged_shapes(16, 16, 200, seed=9)
     As, Bs, Cs, hostAB = make_batch("f32", shapes, seed=9)
     gv, gs, gms = mm.grouped_autotune("f32", As, Bs, Cs, warmup=1, reps=2)
-    assert 0 <= gv < mm.variant_count("f32") and gs in (0, 1, 2) and gms > 0
+    assert 0 <= gv < mm.variant_count("f32") and gs in (0, 1, 2, 3) and gms > 0
     plan = mm.GroupedPlan("f32")
     plan.run(As, Bs, Cs)
     torch.cuda.synchronize()
