@@ -137,8 +137,15 @@ int select_grouped(const mm_problem *probs, int count, mm_method method, int *sc
             return it->second.variant;
         }
     }
-    *schedule = 1;
-    return 1;
+    // untuned batches: 64x64 tiles (fused split for the split methods), one
+    // workgroup per tile -- the autotuner's choice on the 512-problem batch
+    // of dimensions 32..1024
+    *schedule = 3;
+    switch (method) {
+        case MM_F64: return 6;
+        case MM_F32: return 8;
+        default: return 10;
+    }
 }
 
 void store_grouped(const mm_problem *probs, int count, mm_method method, int variant, int schedule, double ms) {
