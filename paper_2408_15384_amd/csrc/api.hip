@@ -84,6 +84,11 @@ static size_t span_bytes(int64_t rows, int64_t cols, int64_t ld, size_t elem) {
     return ((size_t)(rows - 1) * (size_t)ld + (size_t)cols) * elem;
 }
 
+mm_status check_split_k(int64_t K) {
+    if (K > kSplitMaxK) return fail(MM_E_UNSUPPORTED, "split methods take K <= 2^26 - 32");
+    return MM_OK;
+}
+
 mm_status check_gemm_args(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
                           int64_t ldb, const void *C, int64_t ldc, size_t ab_elem, size_t c_elem) {
     if (M < 0 || N < 0 || K < 0) return fail(MM_E_INVAL, "negative dimension");
@@ -201,6 +206,7 @@ size_t mm_split_workspace_bytes(int64_t M, int64_t N, int64_t K, int32_t nprod) 
 static mm_status run_split(int variant, int64_t M, int64_t N, int64_t K, const float *A, int64_t lda,
                            const float *B, int64_t ldb, void *C, int64_t ldc, int32_t c_is_f64, int32_t nprod,
                            void *workspace, size_t workspace_bytes, hipStream_t st) {
+    if (mm_status s = check_split_k(K); s != MM_OK) return s;
     if (K == 0) {
         MM_HIP(launch_fill_zero(C, M, N, ldc, c_is_f64 ? 8 : 4, st));
         return MM_OK;

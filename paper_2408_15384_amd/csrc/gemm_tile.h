@@ -254,7 +254,7 @@ struct TileGemm {
     }
 };
 
-// Direct-to-LDS form of the tile: global_load_lds_dwordx4 moves 16-byte
+// Direct-to-LDS form of the tile: buffer_load_dwordx4 ... lds moves 16-byte
 // chunks of A and B straight into a ring of STAGES LDS buffers (no staging
 // registers, no LDS store instructions), so the loads of K steps kt+1 ..
 // kt+STAGES-1 are in flight while step kt is multiplied.  One
@@ -305,9 +305,10 @@ struct TileGemmDirect {
         return c ^ (((row / KS) & (B_GROUPS - 1)) * B_GROUP_SHIFT);
     }
 
-    static __device__ __forceinline__ void sources(const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
-                                                   int64_t ldb, int64_t M, int64_t N, int64_t m0, int64_t n0,
-                                                   const T *(&src)[LOADS], int64_t (&kstride)[LOADS]) {
+    // Per-lane byte offset of each ring load within the A (BM x BK) or B
+    // (BK x BN) slice of a K step, relative to the slice's first element.
+    static __device__ __forceinline__ void sources(int64_t lda, int64_t ldb, int64_t M, int64_t N, int64_t m0,
+                                                   int64_t n0, uint32_t (&voff)[LOADS]) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -318,66 +319,98 @@ struct TileGemmDirect {
                 const int c = swz_a(row, P % A_CPR);
                 int64_t gr = m0 + row;
                 gr = gr < M ? gr : M - 1;
-                src[j] = A + gr * lda + c * VEC;
-                kstride[j] = 1;                    // a K step moves along the row
+                voff[j] = (uint32_t)(((gr - m0) * lda + c * VEC) * (int64_t)sizeof(T));
             } else {
                 const int Q = P - A_SLOTS;
                 const int row = Q / B_CPR;
                 const int c = swz_b(row, Q % B_CPR);
                 int64_t gc = n0 + c * VEC;
                 gc = gc < N ? gc : N - VEC;
-                src[j] = B + row * ldb + gc;
-                kstride[j] = ldb;                  // a K step moves down the rows
+                voff[j] = (uint32_t)((row * ldb + (gc - n0)) * (int64_t)sizeof(T));
             }
         }
     }
 
-    static __device__ __forceinline__ void issue(const T *const (&src)[LOADS], const int64_t (&kstride)[LOADS],
-                                                 int64_t k0, T *buf) {
+    // The ring loads of one K step as buffer loads into LDS, through one
+    // buffer resource per operand based at the slice.  (Buffer rather than
+    // global LDS loads: the compiler treats a pending global load into LDS as
+    // a flat access and then waits for every outstanding LDS read at each
+    // fragment use; with buffer loads its waits stay per sub-step.)
+    static __device__ __forceinline__ void issue(const T *A_slice, const T *B_slice, const uint32_t (&voff)[LOADS],
+                                                 T *buf) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const __amdgpu_buffer_rsrc_t ra = rsrc(A_slice), rb = rsrc(B_slice);
 #pragma unroll
-        for (int j = 0; j < LOADS; ++j)
-            __builtin_amdgcn_global_load_lds((mm_gvoid *)(src[j] + k0 * kstride[j]),
-                                             (mm_lvoid *)(buf + (j * NWAVES + wave) * 64 * VEC), 16, 0, 0);
+        for (int j = 0; j < LOADS; ++j) {
+            // wave-uniform (A_SLOTS % 64 == 0); per load when A fills whole loads
+            const bool is_a = A_SLOTS % NT == 0 ? j < A_SLOTS / NT : (j * NWAVES + wave) * 64 < A_SLOTS;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(is_a ? ra : rb, (mm_lvoid *)(buf + (j * NWAVES + wave) * 64 * VEC),
+                                                     16, voff[j], 0, 0, 0);
+        }
     }
 
-    static __device__ __forceinline__ void compute(const T *stage, acc_t (&acc)[FM][FN]) {
+    static __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const T *base) {
+        // raw buffer (stride 0), byte range 2^31 - 1, gfx9 default format word
+        return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, 0x7fffffff, 0x00020000);
+    }
+
+    // Fragments of one stage, read one MFMA sub-step ahead of the MFMAs that
+    // use them.  Sub-step s needs b[.][s] and, at the start of each 16-byte A
+    // chunk (s % PER == 0), that chunk of a[.][.]; LDS returns reads in issue
+    // order, so the MFMAs of sub-step s wait only for the reads of s, not for
+    // those of s + 1 issued before them.  `next` (the ring load of a later
+    // stage) is issued after the first reads, off the path to the first MFMA.
+    static constexpr int PER = 16 / (int)sizeof(T);
+    static constexpr int CH = KS * (int)sizeof(T) / 16 > 0 ? KS * (int)sizeof(T) / 16 : 1;
+
+    static __device__ __forceinline__ void read_sub(const T *As, const T *Bs, int s, int wm, int wn, int li, int q,
+                                                    T (&a)[FM][KS], T (&b)[FN][KS]) {
+        typedef T v_t __attribute__((ext_vector_type(PER)));
+        // B first: the first MFMAs of the sub-step need all of b[.][s] but
+        // only the first A chunk
+        const int row = q * KS + s;
+#pragma unroll
+        for (int fn = 0; fn < FN; ++fn) {
+            const int col = wn * WN + fn * 16 + li;
+            b[fn][s] = Bs[row * BN + swz_b(row, col / VEC) * VEC + col % VEC];
+        }
+        if (s % PER == 0) {
+            // A: lane group q holds k = q*KS .. q*KS+KS-1 of its row, CH chunks
+            const int h = s / PER;
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm) {
+                const int arow = wm * WM + fm * 16 + li;
+                const v_t v = *reinterpret_cast<const v_t *>(As + arow * BK + swz_a(arow, q * CH + h) * VEC);
+#pragma unroll
+                for (int e = 0; e < PER; ++e)
+                    if (h * PER + e < KS) a[fm][h * PER + e] = v[e];
+            }
+        }
+    }
+
+    template <typename Next>
+    static __device__ __forceinline__ void compute(const T *stage, acc_t (&acc)[FM][FN], Next next) {
         const int lane = threadIdx.x & 63;
         const int wave = threadIdx.x >> 6;
         const int wm = wave / NWN, wn = wave % NWN;
         const int li = lane & 15, q = lane >> 4;
         const T *As = stage, *Bs = stage + A_SLOTS * VEC;
         T a[FM][KS], b[FN][KS];
-        // A: lane group q holds k = q*KS .. q*KS+KS-1 of its row, KS*sizeof(T)/16 chunks
-        constexpr int CH = KS * (int)sizeof(T) / 16 > 0 ? KS * (int)sizeof(T) / 16 : 1;
-        constexpr int PER = 16 / (int)sizeof(T);
-#pragma unroll
-        for (int fm = 0; fm < FM; ++fm) {
-            const int row = wm * WM + fm * 16 + li;
-#pragma unroll
-            for (int h = 0; h < CH; ++h) {
-                typedef T v_t __attribute__((ext_vector_type(PER)));
-                const v_t v = *reinterpret_cast<const v_t *>(As + row * BK + swz_a(row, q * CH + h) * VEC);
-#pragma unroll
-                for (int e = 0; e < PER && h * PER + e < KS; ++e) a[fm][h * PER + e] = v[e];
-            }
-        }
-#pragma unroll
-        for (int fn = 0; fn < FN; ++fn)
-#pragma unroll
-            for (int s = 0; s < KS; ++s) {
-                const int row = q * KS + s;
-                const int col = wn * WN + fn * 16 + li;
-                b[fn][s] = Bs[row * BN + swz_b(row, col / VEC) * VEC + col % VEC];
-            }
+        read_sub(As, Bs, 0, wm, wn, li, q, a, b);
+        __builtin_amdgcn_sched_barrier(0);
+        next();
         // (no raised priority around the MFMAs here: measured 2-5% slower in
         // this body, where the ring needs no LDS stores between the bursts)
 #pragma unroll
-        for (int s = 0; s < KS; ++s)
+        for (int s = 0; s < KS; ++s) {
+            if (s + 1 < KS) read_sub(As, Bs, s + 1, wm, wn, li, q, a, b);
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
                 for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = MfmaOp<T>::mma(a[fm][s], b[fn][s], acc[fm][fn]);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 
     template <int N_>
@@ -387,8 +420,11 @@ struct TileGemmDirect {
 
     static __device__ __forceinline__ bool eligible(const T *A, int64_t lda, const T *B, int64_t ldb, int64_t N,
                                                     int64_t K) {
+        // the per-lane offsets within a slice must fit the buffer range
+        const int64_t a_span = ((int64_t)(BM - 1) * lda + BK) * (int64_t)sizeof(T);
+        const int64_t b_span = ((int64_t)(BK - 1) * ldb + BN) * (int64_t)sizeof(T);
         return K % BK == 0 && N % VEC == 0 && N >= VEC && lda % VEC == 0 && ldb % VEC == 0 &&
-               ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0);
+               ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && a_span < 0x7fffffff && b_span < 0x7fffffff;
     }
 
     static __device__ __forceinline__ void run(const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
@@ -405,12 +441,12 @@ struct TileGemmDirect {
 #pragma unroll
             for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = acc_t{0, 0, 0, 0};
         const int64_t nkt = K / BK;
-        const T *src[LOADS];
-        int64_t kstride[LOADS];
-        sources(A, lda, B, ldb, M, N, m0, n0, src, kstride);
+        uint32_t voff[LOADS];
+        sources(lda, ldb, M, N, m0, n0, voff);
+        const T *A_tile = A + m0 * lda, *B_tile = B + n0;
 #pragma unroll
         for (int s = 0; s < STAGES - 1; ++s)
-            if (s < nkt) issue(src, kstride, (int64_t)s * BK, smem + s * STAGE_ELEMS);
+            if (s < nkt) issue(A_tile + (int64_t)s * BK, B_tile + (int64_t)s * BK * ldb, voff, smem + s * STAGE_ELEMS);
         for (int64_t kt = 0; kt < nkt; ++kt) {
             const int64_t later = (nkt - 1 - kt) < (STAGES - 2) ? (nkt - 1 - kt) : (STAGES - 2);
             if (later >= 2) wait_vm<2 * LOADS>();
@@ -421,9 +457,10 @@ struct TileGemmDirect {
             // the later stages' loads)
             __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
             __builtin_amdgcn_s_barrier();
-            if (kt + STAGES - 1 < nkt)
-                issue(src, kstride, (kt + STAGES - 1) * BK, smem + ((kt + STAGES - 1) % STAGES) * STAGE_ELEMS);
-            compute(smem + (kt % STAGES) * STAGE_ELEMS, acc);
+            compute(smem + (kt % STAGES) * STAGE_ELEMS, acc, [&] {
+                const int64_t kn = kt + STAGES - 1;
+                if (kn < nkt) issue(A_tile + kn * BK, B_tile + kn * BK * ldb, voff, smem + (kn % STAGES) * STAGE_ELEMS);
+            });
         }
         const int lane = threadIdx.x & 63;
         const int wave = threadIdx.x >> 6;

@@ -369,6 +369,7 @@ static mm_status validate(const mm_problem *probs, int32_t count, mm_method meth
     for (int i = 0; i < count; ++i) {
         const mm_problem &p = probs[i];
         mm_status s = check_gemm_args(p.M, p.N, p.K, p.A, p.lda, p.B, p.ldb, p.C, p.ldc, e, e);
+        if (s == MM_OK && method >= MM_SPLIT_BF16_3) s = check_split_k(p.K);
         if (s != MM_OK) return fail(s, "problem " + std::to_string(i) + ": " + mm_last_error());
     }
     return MM_OK;

@@ -343,6 +343,7 @@ mm_status mm_serve_submit(mm_server *s, const mm_problem *req, mm_method method,
         if (method < MM_F64 || method > MM_SPLIT_BF16_6) return fail(MM_E_INVAL, "unknown method");
         const uint64_t e = elem_bytes(method);
         mm_status st = check_gemm_args(req->M, req->N, req->K, req->A, req->lda, req->B, req->ldb, req->C, req->ldc, e, e);
+        if (st == MM_OK && method >= MM_SPLIT_BF16_3) st = check_split_k(req->K);
         if (st != MM_OK) return st;
         // the size class decides the variant, and the variant whether planes exist
         const int group = (int)method + (req->M * req->N >= s->large_mn ? 4 : 0);

@@ -248,7 +248,7 @@ struct SplitTile {
 
 
 // ---------------------------------------------------------------------------
-// Direct-to-LDS variant: global_load_lds_dwordx4 moves each 16-byte chunk of
+// Direct-to-LDS variant: buffer_load_dwordx4 ... lds moves each 16-byte chunk of
 // the planes straight into LDS (no staging registers), into a ring of STAGES
 // LDS buffers, so the loads of K steps kt+1 .. kt+STAGES-1 are in flight while
 // step kt is multiplied.  One wave-instruction fills 64 consecutive 16-byte
@@ -286,40 +286,51 @@ struct SplitTileDirect {
 
     static __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 2) & 3); }
 
-    // Per-lane source of each load instruction at k = 0; a K step adds k0.
+    // Source of each load instruction at k = 0 (a K step adds k0): the 64
+    // lanes of one instruction fill 16 consecutive rows of one plane, so the
+    // instruction reads through a buffer resource based at the first of those
+    // rows (wave-uniform) and each lane adds a 32-bit byte offset below
+    // 16 * Kp * 2, which the entry points keep below 2^31 (K < 2^26).
+
     static __device__ __forceinline__ void sources(const uint16_t *__restrict__ Ap, int64_t pa_stride,
                                                    const uint16_t *__restrict__ Bt, int64_t pb_stride, int64_t Kp,
                                                    int64_t m0, int64_t n0, int64_t M, int64_t N,
-                                                   const uint16_t *(&src)[LOADS]) {
+                                                   const uint16_t *(&base)[LOADS], uint32_t (&voff)[LOADS]) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int lane = threadIdx.x & 63;
 #pragma unroll
         for (int j = 0; j < LOADS; ++j) {
-            const int P = (j * NWAVES + wave) * 64 + lane;   // this lane's 16-byte slot in the stage
-            const int plane = P / PLANE_CHUNKS;
-            const int rem = P - plane * PLANE_CHUNKS;
-            const int row = rem >> 2;
-            const int c = swz(row, rem & 3);                 // logical chunk stored in this slot
-            if (row < BM) {
-                int64_t gr = m0 + row;
-                gr = gr < M ? gr : M - 1;
-                src[j] = Ap + plane * pa_stride + gr * Kp + c * 8;
-            } else {
-                int64_t gr = n0 + (row - BM);
-                gr = gr < N ? gr : N - 1;
-                src[j] = Bt + plane * pb_stride + gr * Kp + c * 8;
-            }
+            const int P0 = (j * NWAVES + wave) * 64;         // first slot of this instruction (wave-uniform)
+            const int plane = P0 / PLANE_CHUNKS;
+            const int row0 = (P0 - plane * PLANE_CHUNKS) >> 2;
+            const int row = row0 + (lane >> 2);              // 16 rows, all of A or all of B (BM % 16 == 0)
+            const int c = swz(row, lane & 3);                // logical chunk stored in this lane's slot
+            const bool is_a = row0 < BM;
+            const int64_t first = is_a ? m0 + row0 : n0 + (row0 - BM);
+            const int64_t lim = is_a ? M : N;
+            const int64_t g0 = first < lim ? first : lim - 1;
+            int64_t gr = first + (lane >> 2);
+            gr = gr < lim ? gr : lim - 1;
+            base[j] = (is_a ? Ap + plane * pa_stride : Bt + plane * pb_stride) + g0 * Kp;
+            voff[j] = (uint32_t)(((gr - g0) * Kp + c * 8) * 2);
         }
     }
 
     // Issue the loads of the K step at k0 into LDS buffer `buf`: instruction j
-    // of wave w fills the 64 slots of block j*NWAVES + w.
-    static __device__ __forceinline__ void issue(const uint16_t *const (&src)[LOADS], int64_t k0, uint16_t *buf) {
+    // of wave w fills the 64 slots of block j*NWAVES + w.  (Buffer rather than
+    // global LDS loads: the compiler treats a pending global load into LDS as
+    // a flat access and then waits for every outstanding LDS read at each
+    // fragment use; with buffer loads its waits follow the fragments.)
+    static __device__ __forceinline__ void issue(const uint16_t *const (&base)[LOADS], const uint32_t (&voff)[LOADS],
+                                                 int64_t k0, uint16_t *buf) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 #pragma unroll
-        for (int j = 0; j < LOADS; ++j)
-            __builtin_amdgcn_global_load_lds((mm_global_void *)(src[j] + k0),
-                                             (mm_lds_void *)(buf + (j * NWAVES + wave) * 64 * 8), 16, 0, 0);
+        for (int j = 0; j < LOADS; ++j) {
+            const __amdgpu_buffer_rsrc_t r =
+                __builtin_amdgcn_make_buffer_rsrc((void *)(base[j] + k0), (short)0, 0x7fffffff, 0x00020000);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (mm_lds_void *)(buf + (j * NWAVES + wave) * 64 * 8), 16, voff[j],
+                                                     0, 0, 0);
+        }
     }
 
     static __device__ __forceinline__ bf16x8 frag(const uint16_t *stage, int plane, int row, int q) {
@@ -377,11 +388,12 @@ struct SplitTileDirect {
                 corr[fm][fn] = f32x4{0, 0, 0, 0};
             }
         const int64_t nkt = K / BK;
-        const uint16_t *src[LOADS];
-        sources(Ap, pa_stride, Bt, pb_stride, K, m0, n0, M, N, src);
+        const uint16_t *base[LOADS];
+        uint32_t voff[LOADS];
+        sources(Ap, pa_stride, Bt, pb_stride, K, m0, n0, M, N, base, voff);
 #pragma unroll
         for (int s = 0; s < STAGES - 1; ++s)
-            if (s < nkt) issue(src, (int64_t)s * BK, smem + s * STAGE_ELEMS);
+            if (s < nkt) issue(base, voff, (int64_t)s * BK, smem + s * STAGE_ELEMS);
         for (int64_t kt = 0; kt < nkt; ++kt) {
             // stage kt has landed once at most the later stages' loads are pending
             const int64_t later = (nkt - 1 - kt) < (STAGES - 2) ? (nkt - 1 - kt) : (STAGES - 2);
@@ -393,7 +405,8 @@ struct SplitTileDirect {
             // __syncthreads would also wait for the later stages' loads.
             __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));   // lgkmcnt(0) only
             __builtin_amdgcn_s_barrier();
-            if (kt + STAGES - 1 < nkt) issue(src, (kt + STAGES - 1) * BK, smem + ((kt + STAGES - 1) % STAGES) * STAGE_ELEMS);
+            if (kt + STAGES - 1 < nkt)
+                issue(base, voff, (kt + STAGES - 1) * BK, smem + ((kt + STAGES - 1) % STAGES) * STAGE_ELEMS);
             compute(smem + (kt % STAGES) * STAGE_ELEMS, lead, corr);
         }
         // binary64 recombination of the two accumulator sets
