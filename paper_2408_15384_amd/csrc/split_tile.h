@@ -338,22 +338,44 @@ struct SplitTileDirect {
                                                                            row * 32 + swz(row, q) * 8));
     }
 
+    // Plane whose fragments are read just before the products of term t (one
+    // plane ahead of the highest plane term t uses), or -1.
+    static constexpr int read_before(int t) {
+        int last = 0;   // planes 0..last are read before term t (plane 0 up front)
+        for (int u = 0; u < t; ++u) {
+            const int want = (Terms::pa[u] > Terms::pb[u] ? Terms::pa[u] : Terms::pb[u]) + 1;
+            if (want < NP && want > last) last = want;
+        }
+        const int want = (Terms::pa[t] > Terms::pb[t] ? Terms::pa[t] : Terms::pb[t]) + 1;
+        return want < NP && want > last ? want : -1;
+    }
+
+    // The products of one stage.  Fragments are read plane by plane, one
+    // plane ahead of the products that use them, so a product waits only for
+    // its own planes' reads; `next` (the ring load of a later stage) is issued
+    // after the first plane's reads.  Each accumulator still takes the terms
+    // in their fixed order.
+    template <typename Next>
     static __device__ __forceinline__ void compute(const uint16_t *stage, f32x4 (&lead)[FM][FN],
-                                                   f32x4 (&corr)[FM][FN]) {
+                                                   f32x4 (&corr)[FM][FN], Next next) {
         const int lane = threadIdx.x & 63;
         const int wave = threadIdx.x >> 6;
         const int wm = wave / NWN, wn = wave % NWN;
         const int li = lane & 15, q = lane >> 4;
         bf16x8 a[NP][FM], b[NP][FN];
-#pragma unroll
-        for (int p = 0; p < NP; ++p) {
-#pragma unroll
-            for (int fm = 0; fm < FM; ++fm) a[p][fm] = frag(stage, p, wm * WM + fm * 16 + li, q);
+        auto read_plane = [&](int p) {
 #pragma unroll
             for (int fn = 0; fn < FN; ++fn) b[p][fn] = frag(stage, p, BM + wn * WN + fn * 16 + li, q);
-        }
 #pragma unroll
-        for (int t = 0; t < Terms::n; ++t)
+            for (int fm = 0; fm < FM; ++fm) a[p][fm] = frag(stage, p, wm * WM + fm * 16 + li, q);
+        };
+        read_plane(0);
+        __builtin_amdgcn_sched_barrier(0);
+        next();
+#pragma unroll
+        for (int t = 0; t < Terms::n; ++t) {
+            if (read_before(t) >= 0) read_plane(read_before(t));
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
@@ -364,6 +386,8 @@ struct SplitTileDirect {
                         corr[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[Terms::pa[t]][fm], b[Terms::pb[t]][fn],
                                                                                corr[fm][fn], 0, 0, 0);
                 }
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 
     // vmcnt(n) with the other counters left unconstrained (gfx9 encoding).
@@ -405,9 +429,10 @@ struct SplitTileDirect {
             // __syncthreads would also wait for the later stages' loads.
             __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));   // lgkmcnt(0) only
             __builtin_amdgcn_s_barrier();
-            if (kt + STAGES - 1 < nkt)
-                issue(base, voff, (kt + STAGES - 1) * BK, smem + ((kt + STAGES - 1) % STAGES) * STAGE_ELEMS);
-            compute(smem + (kt % STAGES) * STAGE_ELEMS, lead, corr);
+            compute(smem + (kt % STAGES) * STAGE_ELEMS, lead, corr, [&] {
+                if (kt + STAGES - 1 < nkt)
+                    issue(base, voff, (kt + STAGES - 1) * BK, smem + ((kt + STAGES - 1) % STAGES) * STAGE_ELEMS);
+            });
         }
         // binary64 recombination of the two accumulator sets
         const int lane = threadIdx.x & 63;
