@@ -62,16 +62,16 @@ struct Candidate {
     bool plane_pass;
 };
 
-const Candidate kF64Cand[] = {{12, 256, 128, 67.5, false}, {3, 128, 64, 56.3, false}, {6, 64, 64, 60.8, false},
-                              {9, 32, 32, 50.1, false}};
-const Candidate kF32Cand[] = {{12, 256, 128, 136.0, false}, {3, 128, 128, 122.4, false}, {6, 64, 64, 107.4, false},
-                              {10, 32, 32, 69.0, false}};
-const Candidate kSplit3Unfused[] = {{14, 256, 128, 335.3, true}, {6, 128, 128, 277.0, true}, {8, 64, 64, 217.0, true}};
-const Candidate kSplit6Unfused[] = {{9, 256, 128, 203.7, true}, {6, 128, 128, 182.9, true}, {8, 64, 64, 120.9, true}};
-const Candidate kSplit3Cand[] = {{14, 256, 128, 335.3, true}, {6, 128, 128, 277.0, true},  {8, 64, 64, 217.0, true},
-                                 {10, 64, 64, 193.6, false},  {11, 128, 64, 234.7, false}, {12, 128, 128, 202.1, false}};
-const Candidate kSplit6Cand[] = {{9, 256, 128, 203.7, true},  {6, 128, 128, 182.9, true},  {8, 64, 64, 120.9, true},
-                                 {10, 64, 64, 127.8, false},  {11, 128, 64, 147.1, false}, {12, 128, 128, 153.3, false}};
+const Candidate kF64Cand[] = {{12, 256, 128, 69.2, false}, {3, 128, 64, 56.5, false}, {6, 64, 64, 64.5, false},
+                              {9, 32, 32, 53.4, false}};
+const Candidate kF32Cand[] = {{12, 256, 128, 141.7, false}, {3, 128, 128, 126.5, false}, {6, 64, 64, 127.4, false},
+                              {10, 32, 32, 95.0, false}};
+const Candidate kSplit3Unfused[] = {{14, 256, 128, 366.0, true}, {6, 128, 128, 320.0, true}, {8, 64, 64, 221.6, true}};
+const Candidate kSplit6Unfused[] = {{9, 256, 128, 214.0, true}, {6, 128, 128, 190.0, true}, {8, 64, 64, 100.4, true}};
+const Candidate kSplit3Cand[] = {{14, 256, 128, 366.0, true}, {6, 128, 128, 320.0, true},  {8, 64, 64, 221.6, true},
+                                 {10, 64, 64, 191.0, false},  {11, 128, 64, 230.6, false}, {12, 128, 128, 204.5, false}};
+const Candidate kSplit6Cand[] = {{9, 256, 128, 214.0, true},  {6, 128, 128, 190.0, true},  {8, 64, 64, 100.4, true},
+                                 {10, 64, 64, 126.0, false},  {11, 128, 64, 146.4, false}, {12, 128, 128, 151.6, false}};
 
 constexpr double kCUs = 256.0;
 
