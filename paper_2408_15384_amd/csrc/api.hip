@@ -237,7 +237,7 @@ mm_status mm_gemm_split_bf16(int64_t M, int64_t N, int64_t K, const float *A, in
     if (nprod != 3 && nprod != 6) return fail(MM_E_INVAL, "nprod must be 3 or 6");
     mm_status s = check_gemm_args(M, N, K, A, lda, B, ldb, C, ldc, 4, c_is_f64 ? 8 : 4);
     if (s != MM_OK || M == 0 || N == 0) return s;
-    if ((s = check_arch()) != MM_OK) return s;
+    if ((s = check_split_k(K)) != MM_OK || (s = check_arch()) != MM_OK) return s;
     const mm_method m = nprod == 3 ? MM_SPLIT_BF16_3 : MM_SPLIT_BF16_6;
     return run_split(select_variant(m, M, N, K), M, N, K, A, lda, B, ldb, C, ldc, c_is_f64, nprod, workspace,
                      workspace_bytes, (hipStream_t)stream);
@@ -275,8 +275,8 @@ mm_status mm_gemm_ex(mm_method method, mm_op opa, mm_op opb, int64_t M, int64_t 
     const size_t cb = span_bytes(M, N, ldc, e);
     if (K > 0 && (overlaps(C, cb, A, span_bytes(ar, ac, lda, e)) || overlaps(C, cb, B, span_bytes(br, bc, ldb, e))))
         return fail(MM_E_INVAL, "C overlaps A or B");
-    mm_status s = check_arch();
-    if (s != MM_OK) return s;
+    mm_status s = method >= MM_SPLIT_BF16_3 ? check_split_k(K) : MM_OK;
+    if (s != MM_OK || (s = check_arch()) != MM_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     if (K == 0) {
         MM_HIP(launch_fill_zero(C, M, N, ldc, (int)e, st));
@@ -436,6 +436,7 @@ mm_status mm_gemm_variant(mm_method method, int32_t variant, int64_t M, int64_t 
     const size_t e = method == MM_F64 ? 8 : 4;
     mm_status s = check_gemm_args(M, N, K, A, lda, B, ldb, C, ldc, e, e);
     if (s != MM_OK || M == 0 || N == 0) return s;
+    if (method >= MM_SPLIT_BF16_3 && (s = check_split_k(K)) != MM_OK) return s;
     if ((s = check_arch()) != MM_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     switch (method) {

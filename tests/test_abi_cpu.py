@@ -76,6 +76,24 @@ def test_invalid_arguments_without_gpu(lib):
     assert lib.mm_gemm_grouped_config(probs, 0, api.MM_F64, 0, 3, None, None) == api.MM_OK
 
 
+def test_split_k_limit_without_gpu(lib):
+    # the split tiles address 16 plane rows with 32-bit byte offsets: K above
+    # 2^26 - 32 is refused by every entry point that takes a split method,
+    # before any device work (the addresses below are never dereferenced)
+    kmax = (1 << 26) - 32
+    K = kmax + 1
+    a, b, c = 1 << 40, 1 << 41, 1 << 42
+    E = api.MM_E_UNSUPPORTED
+    assert lib.mm_gemm_split_bf16(2, 2, K, a, K, b, 2, c, 2, 0, 6, None, 0, None) == E
+    assert b"2^26" in lib.mm_last_error()
+    for m in (api.MM_SPLIT_BF16_3, api.MM_SPLIT_BF16_6):
+        assert lib.mm_gemm_ex(m, 0, 0, 2, 2, K, a, K, b, 2, c, 2, None, 0, None) == E
+        assert lib.mm_gemm_variant(m, 0, 2, 2, K, a, K, b, 2, c, 2, None, 0, None) == E
+        probs = (api.Problem * 1)(api.Problem(2, 2, K, a, K, b, 2, c, 2))
+        assert lib.mm_gemm_grouped(probs, 1, m, None, None) == E
+        assert b"problem 0" in lib.mm_last_error()
+
+
 def test_variant_tables(lib):
     for m in ("f64", "f32", "split3", "split6"):
         n = api.variant_count(m)
