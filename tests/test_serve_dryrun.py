@@ -176,3 +176,18 @@ def test_invalid_requests_rejected():
         api.Server(budget_bytes=1 << 30, slots=0)
     with pytest.raises(api.MMError):
         api.Server(budget_bytes=1 << 30, slots=17)
+
+
+def test_split_request_with_k_beyond_limit_is_refused():
+    # split requests address 16 plane rows with 32-bit offsets: K above
+    # 2^26 - 32 is refused at submission; binary64 has no such limit
+    K = (1 << 26) - 31
+    srv = api.Server(budget_bytes=1 << 62, slots=1, dry_run_tflops=1e6)
+    try:
+        with pytest.raises(api.MMError) as e:
+            submit(srv, 0, 2, 2, K, method=api.MM_SPLIT_BF16_6)
+        assert e.value.status == api.MM_E_UNSUPPORTED
+        rid = submit(srv, 1, 2, 2, K, method=api.MM_F64)
+        assert srv.wait(rid)[0] == api.MM_OK
+    finally:
+        srv.close()
