@@ -103,6 +103,45 @@ def test_direct_tile_shapes(mm, method, shape):
         assert np.array_equal(host(C).astype(np.float64), oracle.gemm(Ai, Bi)), f"variant {v}"
 
 
+def _span_limit_ld(rows_before_last, extra, elem):
+    """Largest leading dimension (a multiple of the 16-byte vector) whose
+    slice span (rows_before_last * ld + extra) * elem stays below 2^31 - 1."""
+    vec = 16 // elem
+    ld = ((2 ** 31 - 1) // elem - extra) // rows_before_last
+    ld -= ld % vec
+    while (rows_before_last * ld + extra) * elem >= 2 ** 31 - 1:
+        ld -= vec
+    return ld
+
+
+@pytest.mark.parametrize("method,variant", [("f64", 12), ("f32", 11)])
+def test_direct_tile_huge_leading_dimensions(mm, method, variant):
+    """The direct tiles address a K slice through one buffer resource per
+    operand with 32-bit lane offsets.  A leading dimension at the largest
+    value whose slice still fits (offsets near 2^31) takes the direct path;
+    one vector more takes the register tile.  Both match the oracle."""
+    bm, bn, bk = mm.variant_info(method, variant)
+    dt = torch.float64 if method == "f64" else torch.float32
+    elem = 8 if method == "f64" else 4
+    M, N, K = bm + 44, bn + 8, 2 * bk
+    kind = "uniform_f64" if method == "f64" else "uniform_f32"
+    A, B = I.pair(kind, M, N, K, seed=M + N)
+    u = oracle.U_F64 if method == "f64" else oracle.U_F32
+    vec = 16 // elem
+    lda_in = _span_limit_ld(bm - 1, bk, elem)
+    ldb_in = _span_limit_ld(bk - 1, bn, elem)
+    for lda, ldb in ((lda_in, N), (lda_in + vec, N), (K, ldb_in), (K, ldb_in + vec)):
+        Ab = torch.empty((M, lda), dtype=dt, device="cuda")
+        Bb = torch.empty((K, ldb), dtype=dt, device="cuda")
+        Ab[:, :K] = dev(A)
+        Bb[:, :N] = dev(B)
+        C = torch.full((M, N), float("nan"), dtype=dt, device="cuda")
+        mm.gemm_variant(method, variant, Ab[:, :K], Bb[:, :N], C)
+        assert_within_bound(host(C), A, B, u)
+        del Ab, Bb, C
+        torch.cuda.empty_cache()
+
+
 def test_f64_leading_dims_and_misaligned(mm):
     M, N, K = 70, 45, 37
     A, B = I.pair("uniform_f64", M, N, K, seed=4)
