@@ -297,6 +297,38 @@ def test_split_variants_bit_identical(mm, nprod, shape):
 
 # ------------------------------------------------------------------ residual
 
+def test_split_at_the_k_limit_bit_exact(mm):
+    """Split products at the largest K the split methods take (2^26 - 32):
+    the direct tiles' lane offsets over 16 plane rows reach ~2^31 bytes.
+    Integer-valued operands with a sparse A keep every partial sum exact in
+    FP32, so every variant must equal the oracle bit for bit."""
+    K = (1 << 26) - 32
+    M, N = 16, 16
+    rng = np.random.default_rng(26)
+    nnz = 4096
+    cols = np.sort(np.concatenate([rng.choice(K - 64, size=(M, nnz - 64)), np.tile(np.arange(K - 64, K), (M, 1))], axis=1), axis=1)
+    vals = rng.integers(-8, 9, size=cols.shape).astype(np.float32)
+    A = torch.zeros((M, K), dtype=torch.float32, device="cuda")
+    rows = np.repeat(np.arange(M), cols.shape[1])
+    A.index_put_((torch.from_numpy(rows).cuda(), torch.from_numpy(cols.reshape(-1)).cuda()),
+                 torch.from_numpy(vals.reshape(-1)).cuda(), accumulate=True)
+    kk = torch.arange(K, device="cuda", dtype=torch.int64).view(K, 1)
+    jj = torch.arange(N, device="cuda", dtype=torch.int64).view(1, N)
+    B = (((kk * 7 + jj * 3) % 17) - 8).to(torch.float32)          # integers in [-8, 8]
+    R = oracle.gemm(host(A).astype(np.float64), host(B).astype(np.float64))
+    assert np.abs(R).max() < 2 ** 24                                # every partial sum exact in FP32
+    ws = torch.empty(mm.split_workspace_bytes(M, N, K, 6), dtype=torch.uint8, device="cuda")
+    for method in ("split3", "split6"):
+        # the default choice, and the 64x64 and 256x128 direct-ring variants
+        for v in (None, 8, 14):
+            C = torch.full((M, N), float("nan"), dtype=torch.float32, device="cuda")
+            if v is None:
+                mm.gemm_split_bf16(A, B, 3 if method == "split3" else 6, C=C, workspace=ws)
+            else:
+                mm.gemm_variant(method, v, A, B, C, workspace=ws)
+            assert np.array_equal(host(C).astype(np.float64), R), f"{method} variant {v}"
+
+
 def test_residual_exact_and_planted(mm):
     M, N, K = 90, 70, 110
     A, B = I.pair("int_f64", M, N, K, seed=5)
