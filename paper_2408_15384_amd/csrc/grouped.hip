@@ -70,6 +70,18 @@ __device__ __forceinline__ int64_t uniform(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
+// One workgroup per tile: workgroups are dispatched to the 8 XCDs round-
+// robin.  Chunks of kChunk consecutive tiles (mostly of one problem, sharing
+// its A row panel) go to one XCD, whose L2 then serves the shared panels;
+// chunk c goes to XCD c % 8, so every XCD still takes heavy and light work in
+// the order of the tile map.  A bijection on [0, round_up(tiles, 8 kChunk)).
+constexpr int kChunk = 8;
+__device__ __forceinline__ int64_t chunked_tile(int64_t bid) {
+    const int64_t xcd = bid % 8, local = bid / 8;
+    return ((local / kChunk) * 8 + xcd) * kChunk + local % kChunk;
+}
+inline int64_t chunked_grid(int64_t tiles) { return (tiles + 8 * kChunk - 1) / (8 * kChunk) * (8 * kChunk); }
+
 constexpr int kOwnerCap = 1024;     // problems whose prefix sums are staged in LDS
 constexpr int kJobCap = 2048;       // split jobs likewise
 
@@ -139,7 +151,7 @@ __global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 && TG::LDS_ELEMS * sizeof(
             t = next_tile(t, counter, ticket, &slot);
         }
     } else {
-        const int64_t t = blockIdx.x;
+        const int64_t t = chunked_tile(blockIdx.x);
         if (t < total_tiles)
             grouped_dense_tile<TG, T>(descs, uniform(find_owner(descs, (const int32_t *)nullptr, false, count, t)), t,
                                       smem);
@@ -161,7 +173,7 @@ __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void grouped_spl
             t = next_tile(t, counter, ticket, &slot);
         }
     } else {
-        const int64_t t = blockIdx.x;
+        const int64_t t = chunked_tile(blockIdx.x);
         if (t < total_tiles)
             grouped_split_tile<ST>(descs, uniform(find_owner(descs, (const int32_t *)nullptr, false, count, t)), t,
                                    smem);
@@ -348,15 +360,15 @@ hipError_t grouped_enqueue(mm_method method, int variant, bool persistent, const
     if (ndesc == 0) return hipSuccess;
     const KernelInfo k = kernel_for(method, variant, persistent);
     if (!k.fn) return hipErrorInvalidValue;
-    if (!persistent && total_tiles > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    if (!persistent && chunked_grid(total_tiles) > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     if (njobs > 0 && split_tiles > 0) {
         int64_t g = split_tiles < 4096 ? split_tiles : 4096;
         hipLaunchKernelGGL(grouped_split_kernel, dim3((unsigned)g), dim3(256), 0, st, d_jobs, njobs, split_tiles);
     }
     if (!persistent) d_counter = nullptr;
     if (d_counter) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, d_counter);
-    int64_t grid = persistent ? persistent_grid(method, variant, k.fn, k.nt) : total_tiles;
-    if (grid > total_tiles) grid = total_tiles;
+    int64_t grid = persistent ? persistent_grid(method, variant, k.fn, k.nt) : chunked_grid(total_tiles);
+    if (persistent && grid > total_tiles) grid = total_tiles;
     void *args[] = {(void *)&d_descs, (void *)&ndesc, (void *)&total_tiles, (void *)&d_counter};
     return hipLaunchKernel(k.fn, dim3((unsigned)grid), dim3(k.nt), args, 0, st);
 }
@@ -591,8 +603,9 @@ mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out
     if (tiles_out) *tiles_out = plan->layout.total_tiles;
     if (grid_out) {
         const KernelInfo k = kernel_for(plan->method, plan->variant);
-        int64_t g = plan->schedule == 3 ? plan->layout.total_tiles : persistent_grid(plan->method, plan->variant, k.fn, k.nt);
-        if (g > plan->layout.total_tiles) g = plan->layout.total_tiles;
+        int64_t g = plan->schedule == 3 ? chunked_grid(plan->layout.total_tiles)
+                                        : persistent_grid(plan->method, plan->variant, k.fn, k.nt);
+        if (plan->schedule != 3 && g > plan->layout.total_tiles) g = plan->layout.total_tiles;
         *grid_out = (int32_t)(g < 0x7fffffffLL ? g : 0x7fffffffLL);
     }
     if (uses_graph_out) *uses_graph_out = plan->exec != nullptr;
