@@ -100,13 +100,25 @@ __device__ __forceinline__ int64_t next_tile(int64_t cur, const int *counter, in
     return uniform(*slot);
 }
 
+// Tile coordinates of a problem's local tile index: column-major within
+// groups of two tile rows, so that runs of consecutive tiles (which the
+// one-workgroup-per-tile form keeps on one XCD) share A and B panels.
+__device__ __forceinline__ void local_tile(int64_t local, int64_t tiles_m, int64_t tiles_n, int64_t *tm, int64_t *tn) {
+    const int64_t per_group = 2 * tiles_n;
+    const int64_t first_m = (local / per_group) * 2;
+    const int64_t gsize = tiles_m - first_m < 2 ? tiles_m - first_m : 2;
+    const int64_t in = local % per_group;
+    *tm = uniform(first_m + in % gsize);
+    *tn = uniform(in / gsize);
+}
+
 // One tile of a grouped launch: decode the owner's descriptor and run the
 // single-problem tile body on it.
 template <typename TG, typename T>
 __device__ __forceinline__ void grouped_dense_tile(const GroupedDesc *__restrict__ descs, int own, int64_t t, T *smem) {
     const GroupedDesc &d = descs[own];
-    const int64_t local = t - d.tile_begin;
-    const int64_t tm = uniform(local / d.tiles_n), tn = uniform(local % d.tiles_n);
+    int64_t tm, tn;
+    local_tile(t - d.tile_begin, d.tiles_m, d.tiles_n, &tm, &tn);
     const bool vec_ok = (d.lda % TG::VEC == 0) && (d.ldb % TG::VEC == 0) && ((uintptr_t)d.A % 16 == 0) &&
                         ((uintptr_t)d.B % 16 == 0);
     TG::run((const T *)d.A, d.lda, (const T *)d.B, d.ldb, (T *)d.C, d.ldc, d.M, d.N, d.K, tm, tn, vec_ok, smem);
@@ -116,8 +128,8 @@ template <typename ST>
 __device__ __forceinline__ void grouped_split_tile(const GroupedDesc *__restrict__ descs, int own, int64_t t,
                                                    uint16_t *smem) {
     const GroupedDesc &d = descs[own];
-    const int64_t local = t - d.tile_begin;
-    const int64_t tm = uniform(local / d.tiles_n), tn = uniform(local % d.tiles_n);
+    int64_t tm, tn;
+    local_tile(t - d.tile_begin, d.tiles_m, d.tiles_n, &tm, &tn);
     if constexpr (ST::FUSED) {
         // descriptors hold the FP32 operands themselves
         ST::run_fused((const float *)d.A, d.lda, (const float *)d.B, d.ldb, d.C, d.ldc, 0, d.M, d.N, d.K, tm, tn, smem);
@@ -304,6 +316,7 @@ void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_met
         d.C = p.C;
         d.ldc = p.ldc;
         d.tiles_n = (int32_t)cdiv(p.N, bn);
+        d.tiles_m = (int32_t)cdiv(p.M, bm);
         d.tile_begin = L->total_tiles;
         L->total_tiles += cdiv(p.M, bm) * d.tiles_n;
         if (split) {

@@ -110,7 +110,7 @@ struct GroupedDesc {
     void *C; int64_t ldc;
     int64_t tile_begin;   // exclusive prefix sum of tile counts
     int32_t tiles_n;      // tiles along N
-    int32_t pad;
+    int32_t tiles_m;      // tiles along M
 };
 
 // One split job of a grouped launch: the planes of one operand.
