@@ -16,8 +16,9 @@ Also reported in the same line (context, not the headline):
     input sets, each with its error against the binary64 oracle (sampled rows)
     and its binary64 residual probe;
   * grouped: 512 FP32 problems with dimensions log-uniform on [32, 1024], one
-    graph-replayed persistent launch, plain FP32 versus split, with the
-    residual probe of every result and the oracle's error on a sample;
+    graph-replayed launch (tile variant and schedule autotuned), plain FP32
+    versus split, with the residual probe of every result and the oracle's
+    error on a sample;
   * serving: Poisson arrivals of GEMM requests (dimensions log-uniform on
     [64, 4096], half binary64, half FP32-accurate split), operands resident on
     the device, a 64 GiB admission budget; p50/p99 latency and throughput,
@@ -28,7 +29,8 @@ Also reported in the same line (context, not the headline):
   * shard: one GPU's share (1024 rows) of a row-sharded 8192 product;
   * layouts: transposed operands (NN, NT, TN, TT) at 8192;
   * paper sizes: the paper's experiment (Box-Muller inputs, 32..1024), GPU
-    against the oracle on one and on all host cores.
+    against the oracle on one and on all host cores, and the oracle's thread
+    scaling (1, 2, 4, 8, 16 threads) at 1024.
 
 Usage: python bench.py [--gpus 1] [--steps 15] [--warmup 3]
                        [--sections peak,precision,grouped,serving,strassen,shard,layouts,paper|none]
@@ -552,6 +554,20 @@ def paper_section(torch, mm, sizes=(32, 64, 128, 256, 512, 1024), reps=15):
                 ts.append(time.perf_counter() - t0)
             row[f"oracle_{threads}t_s"] = float(np.mean(ts))
             row[f"oracle_{threads}t_reps"] = r
+        if n == 1024:
+            # the paper's thread scaling at 1024 (its section VII): the oracle
+            # on 1, 2, 4, 8 and 16 host threads (one run each above 1 and 16)
+            scale = {1: row["oracle_1t_s"], cores: row[f"oracle_{cores}t_s"]}
+            for threads in (2, 4, 8, 16):
+                if threads in scale or threads > cores:
+                    continue
+                oracle.set_threads(threads)
+                t0 = time.perf_counter()
+                oracle.gemm(A, B)
+                scale[threads] = time.perf_counter() - t0
+            row["oracle_thread_scaling_s"] = {str(k): v for k, v in sorted(scale.items())}
+            row["paper_thread_scaling_s"] = {"gcc": {"1": 9.67, "16": 0.88}, "intel": {"1": 1.59, "16": 0.12}}
+            log("  paper sizes n=1024 oracle threads " + ", ".join(f"{k}: {v:.3g} s" for k, v in sorted(scale.items())))
         bound = oracle.elementwise_bound(oracle.abs_product(A, B), n, oracle.U_F64)
         row["max_err_over_bound"] = float((np.abs(C - R) / np.maximum(bound, 1e-300)).max())
         row["paper_gcc_O3_serial_s"] = PAPER_SERIAL_O3["gcc"][n]
