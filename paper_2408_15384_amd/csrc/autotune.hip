@@ -62,9 +62,9 @@ struct Candidate {
     bool plane_pass;
 };
 
-const Candidate kF64Cand[] = {{12, 256, 128, 69.2, false}, {3, 128, 64, 56.5, false}, {6, 64, 64, 64.5, false},
-                              {9, 32, 32, 53.4, false}};
-const Candidate kF32Cand[] = {{12, 256, 128, 141.7, false}, {3, 128, 128, 126.5, false}, {6, 64, 64, 127.4, false},
+const Candidate kF64Cand[] = {{12, 256, 128, 69.2, false}, {3, 128, 64, 56.5, false}, {13, 64, 64, 64.1, false},
+                              {14, 32, 32, 52.0, false}};
+const Candidate kF32Cand[] = {{12, 256, 128, 141.7, false}, {3, 128, 128, 126.5, false}, {8, 64, 64, 141.0, false},
                               {10, 32, 32, 95.0, false}};
 const Candidate kSplit3Unfused[] = {{14, 256, 128, 366.0, true}, {6, 128, 128, 320.0, true}, {8, 64, 64, 221.6, true}};
 const Candidate kSplit6Unfused[] = {{9, 256, 128, 214.0, true}, {6, 128, 128, 190.0, true}, {8, 64, 64, 100.4, true}};

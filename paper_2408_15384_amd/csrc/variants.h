@@ -21,7 +21,9 @@
     X(9, 32, 32, 16, 16, 16, 13)      \
     X(10, 32, 32, 16, 16, 16, 0)      \
     X(11, 128, 256, 16, 64, 64, 13)   \
-    X(12, 256, 128, 16, 64, 64, 12)
+    X(12, 256, 128, 16, 64, 64, 12)   \
+    X(13, 64, 64, 16, 32, 32, 14)     \
+    X(14, 32, 32, 16, 16, 16, 14)
 
 #define MM_F32_VARIANTS(X)            \
     X(0, 128, 128, 16, 64, 64, 0)     \
