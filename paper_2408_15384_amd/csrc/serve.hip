@@ -64,6 +64,7 @@ struct Slot {
     // staging
     char *ws = nullptr;       // split workspace, grown when a batch needs more
     size_t ws_cap = 0;
+    std::vector<char *> ws_retired;   // outgrown workspaces, freed with the server
     GroupedDesc *d_descs = nullptr;
     SplitJob *d_jobs = nullptr;
     GroupedDesc *h_descs = nullptr;
@@ -182,12 +183,16 @@ static mm_status launch(mm_server *s, Slot &slot, const std::vector<uint64_t> &i
         ws_need += (L[g].ws_bytes + 255) & ~(size_t)255;
     }
     if (ws_need > slot.ws_cap) {
-        // the slot is idle (its previous launch has retired), so its old buffer is free
-        if (slot.ws) MM_HIP(hipFree(slot.ws));
-        slot.ws = nullptr;
-        slot.ws_cap = 0;
-        const size_t want = ws_need + ws_need / 2;
-        MM_HIP(hipMalloc((void **)&slot.ws, want));
+        // Growth doubles, and the outgrown buffer is kept until the server is
+        // destroyed: hipFree waits for the whole device, which stalled every
+        // other slot's launches (served p99 4.1-7.2 ms against 2.7-3.5 ms
+        // with tiles that need no workspace).  Kept buffers total less than
+        // the largest one.
+        char *fresh = nullptr;
+        const size_t want = std::max(ws_need, 2 * slot.ws_cap);
+        MM_HIP(hipMalloc((void **)&fresh, want));
+        if (slot.ws) slot.ws_retired.push_back(slot.ws);
+        slot.ws = fresh;
         slot.ws_cap = want;
     }
     size_t ws_off = 0;
@@ -274,6 +279,7 @@ static void release(mm_server *s) {
         if (slot.done) (void)hipEventDestroy(slot.done);
         if (slot.stream) (void)hipStreamDestroy(slot.stream);
         if (slot.ws) (void)hipFree(slot.ws);
+        for (char *w : slot.ws_retired) (void)hipFree(w);
         if (slot.d_descs) (void)hipFree(slot.d_descs);
         if (slot.d_jobs) (void)hipFree(slot.d_jobs);
         if (slot.h_descs) (void)hipHostFree(slot.h_descs);
