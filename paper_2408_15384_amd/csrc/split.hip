@@ -15,34 +15,68 @@ namespace mm {
 
 
 // ------------------------------------------------------------------ split pass
+// Eight bfloat16 values of one plane row as one 16-byte store, or element by
+// element where the chunk is not 16-byte aligned or would pass the row end.
+typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_ua __attribute__((ext_vector_type(4), aligned(4)));   // element-aligned vector load
+
+__device__ __forceinline__ void store_plane_chunk(uint16_t *dst, const uint16_t (&h)[8], int n, bool vec) {
+    if (vec && n == 8) {
+        u16x8_t v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = h[e];
+        *reinterpret_cast<u16x8_t *>(dst) = v;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (e < n) dst[e] = h[e];
+    }
+}
+
 // Row-major planes with rows of ldp >= cols elements (columns cols..ldp-1
-// written as zero): each thread splits 4 consecutive elements of one row.
+// written as zero): each thread splits 8 consecutive elements of one row,
+// read as two 16-byte loads when they are all inside the row (the memory
+// system runs in unaligned mode, so element alignment suffices) and written
+// as one 16-byte store per plane.
 __global__ void split_rows_kernel(const float *__restrict__ X, int64_t ldx, int64_t rows, int64_t cols, int nplanes,
                                   uint16_t *__restrict__ planes, int64_t plane_stride, int64_t ldp) {
-    const int64_t quads_per_row = (ldp + 3) / 4;
-    const int64_t total = rows * quads_per_row;
+    const int64_t chunks_per_row = (ldp + 7) / 8;
+    const int64_t total = rows * chunks_per_row;
+    const bool vec_store = ldp % 8 == 0 && plane_stride % 8 == 0 && (uintptr_t)planes % 16 == 0;
     for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < total; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t r = t / quads_per_row;
-        const int64_t c0 = (t % quads_per_row) * 4;
-        const float *src = X + r * ldx + c0;
-        float v[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) v[e] = (c0 + e < cols) ? src[e] : 0.f;
-        for (int p = 0; p < nplanes; ++p) {
-            uint16_t *dst = planes + p * plane_stride + r * ldp + c0;
+        const int64_t r = t / chunks_per_row;
+        const int64_t c0 = (t % chunks_per_row) * 8;
+        const gptr<const float> src = (gptr<const float>)(X + r * ldx + c0);
+        float v[8];
+        if (c0 + 8 <= cols) {
+            const f32x4_ua lo = *(const __attribute__((address_space(1))) f32x4_ua *)src;
+            const f32x4_ua hi = *(const __attribute__((address_space(1))) f32x4_ua *)(src + 4);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const uint16_t h = split_bf16_bits(v[e]);
-                if (c0 + e < ldp) dst[e] = h;
-                v[e] = v[e] - split_bf16_value(h);
+                v[e] = lo[e];
+                v[4 + e] = hi[e];
             }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = (c0 + e < cols) ? src[e] : 0.f;
+        }
+        const int n = ldp - c0 < 8 ? (int)(ldp - c0) : 8;
+        for (int p = 0; p < nplanes; ++p) {
+            uint16_t h[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                h[e] = split_bf16_bits(v[e]);
+                v[e] = v[e] - split_bf16_value(h[e]);
+            }
+            store_plane_chunk(planes + p * plane_stride + r * ldp + c0, h, n, vec_store);
         }
     }
 }
 
 // Transposed planes (rows of X^T hold ldp >= rows elements, the tail written
-// as zero): 64 x 64 tiles through LDS so both the FP32 reads (along a row of
-// X) and the bfloat16 writes (along a row of X^T) are coalesced.
+// as zero): 64 x 64 tiles through LDS so that the FP32 reads run along rows of
+// X and the bfloat16 writes along rows of X^T, 8 values (16 bytes) per thread
+// and plane.
 __global__ __launch_bounds__(256) void split_transpose_kernel(const float *__restrict__ X, int64_t ldx, int64_t rows,
                                                               int64_t cols, int nplanes, uint16_t *__restrict__ planes,
                                                               int64_t plane_stride, int64_t ldp) {
@@ -50,21 +84,46 @@ __global__ __launch_bounds__(256) void split_transpose_kernel(const float *__res
     const int64_t tiles_c = (cols + 63) / 64;
     const int64_t r0 = (blockIdx.x / tiles_c) * 64;
     const int64_t c0 = (blockIdx.x % tiles_c) * 64;
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-    for (int i = ty; i < 64; i += 4) {
-        const int64_t r = r0 + i, c = c0 + tx;
-        tile[i][tx] = (r < rows && c < cols) ? X[r * ldx + c] : 0.f;
+    // 16 threads read one 64-float row segment as 16-byte loads, 4 rows per
+    // pass of the 256 threads
+    const int cq = (threadIdx.x & 15) * 4, rq = threadIdx.x >> 4;
+    for (int i = rq; i < 64; i += 16) {
+        const int64_t r = r0 + i, c = c0 + cq;
+        float v[4] = {0.f, 0.f, 0.f, 0.f};
+        if (r < rows) {
+            const gptr<const float> src = (gptr<const float>)(X + r * ldx + c);
+            if (c + 4 <= cols) {
+                const f32x4_ua q = *(const __attribute__((address_space(1))) f32x4_ua *)src;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = q[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (c + e < cols) v[e] = src[e];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tile[i][cq + e] = v[e];
     }
     __syncthreads();
-    // output element (c, r) of X^T: thread tx walks r
-    for (int j = ty; j < 64; j += 4) {
-        const int64_t c = c0 + j, r = r0 + tx;
+    const bool vec_store = ldp % 8 == 0 && plane_stride % 8 == 0 && (uintptr_t)planes % 16 == 0;
+    // output row c of X^T, entries r .. r+7: 8 consecutive threads cover 64 r
+    for (int k = threadIdx.x; k < 64 * 8; k += 256) {
+        const int cl = k >> 3, rl = (k & 7) * 8;
+        const int64_t c = c0 + cl, r = r0 + rl;
         if (c >= cols || r >= ldp) continue;
-        float v = tile[tx][j];
+        float v[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) v[e] = tile[rl + e][cl];
+        const int n = ldp - r < 8 ? (int)(ldp - r) : 8;
         for (int p = 0; p < nplanes; ++p) {
-            const uint16_t h = split_bf16_bits(v);
-            planes[p * plane_stride + c * ldp + r] = h;
-            v = v - split_bf16_value(h);
+            uint16_t h[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                h[e] = split_bf16_bits(v[e]);
+                v[e] = v[e] - split_bf16_value(h[e]);
+            }
+            store_plane_chunk(planes + p * plane_stride + c * ldp + r, h, n, vec_store);
         }
     }
 }
@@ -80,7 +139,7 @@ hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx,
                            nplanes, planes, plane_stride, ldp);
     } else {
         if (ldp < cols) return hipErrorInvalidConfiguration;
-        int64_t blocks = (rows * ((ldp + 3) / 4) + 255) / 256;
+        int64_t blocks = (rows * ((ldp + 7) / 8) + 255) / 256;
         if (blocks > 1 << 20) blocks = 1 << 20;
         hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, X, ldx, rows, cols,
                            nplanes, planes, plane_stride, ldp);
