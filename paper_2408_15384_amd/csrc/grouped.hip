@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void grouped_split_kernel(const SplitJob *__re
                                                             int64_t total_tiles) {
     __shared__ float tile[64][65];
     __shared__ int32_t s_begin[kJobCap];
-    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int cq = (threadIdx.x & 15) * 4, rq = threadIdx.x >> 4;
     const bool cached = stage_begins<kJobCap>(jobs, njobs, total_tiles, s_begin);
     for (int64_t t = blockIdx.x; t < total_tiles; t += gridDim.x) {
         const SplitJob &j = jobs[uniform(find_owner(jobs, s_begin, cached, njobs, t))];
@@ -204,25 +204,41 @@ __global__ __launch_bounds__(256) void grouped_split_kernel(const SplitJob *__re
         const gptr<uint16_t> planes = (gptr<uint16_t>)j.planes;
         const int64_t local = t - j.tile_begin;
         const int64_t r0 = (local / j.tiles_c) * 64, c0 = (local % j.tiles_c) * 64;
-        for (int i = ty; i < 64; i += 4) {
-            const int64_t r = r0 + i, c = c0 + tx;
-            tile[i][tx] = (r < j.rows && c < j.cols) ? X[r * j.ldx + c] : 0.f;
-        }
-        __syncthreads();
-        for (int i = ty; i < 64; i += 4) {
-            // transposed: output row c0+i walks r; plain: output row r0+i walks c.
-            // Output rows hold j.ldp elements; the tail past the data is zero.
-            const int64_t r = j.transpose ? r0 + tx : r0 + i;
-            const int64_t c = j.transpose ? c0 + i : c0 + tx;
-            if (j.transpose ? (r < j.ldp && c < j.cols) : (r < j.rows && c < j.ldp)) {
-                float v = j.transpose ? tile[tx][i] : tile[i][tx];
-                const int64_t o = j.transpose ? c * j.ldp + r : r * j.ldp + c;
-                for (int p = 0; p < j.nplanes; ++p) {
-                    const uint16_t h = split_bf16_bits(v);
-                    planes[p * j.pstride + o] = h;
-                    v = v - split_bf16_value(h);
+        // 16 threads read one 64-float row segment as 16-byte loads
+        for (int i = rq; i < 64; i += 16) {
+            const int64_t r = r0 + i, c = c0 + cq;
+            float v[4] = {0.f, 0.f, 0.f, 0.f};
+            if (r < j.rows) {
+                const gptr<const float> src = X + r * j.ldx + c;
+                if (c + 4 <= j.cols) {
+                    const f32x4 q = load_f32x4_ea(src);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = q[e];
+                } else {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        if (c + e < j.cols) v[e] = src[e];
                 }
             }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) tile[i][cq + e] = v[e];
+        }
+        __syncthreads();
+        // 8 consecutive outputs per thread and plane, one 16-byte store when
+        // aligned.  Transposed: output row c0+a walks r from r0+b; plain:
+        // output row r0+a walks c from c0+b.  Output rows hold j.ldp elements;
+        // the tail past the data is zero.
+        const bool vec = j.ldp % 8 == 0 && j.pstride % 8 == 0 && (uintptr_t)j.planes % 16 == 0;
+        for (int k = threadIdx.x; k < 64 * 8; k += 256) {
+            const int a = k >> 3, b = (k & 7) * 8;
+            const int64_t row = j.transpose ? c0 + a : r0 + a;            // output row
+            const int64_t col = j.transpose ? r0 + b : c0 + b;            // first output column
+            if (row >= (j.transpose ? j.cols : j.rows) || col >= j.ldp) continue;
+            float v[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) v[e] = j.transpose ? tile[b + e][a] : tile[a][b + e];
+            const int n = j.ldp - col < 8 ? (int)(j.ldp - col) : 8;
+            for (int p = 0; p < j.nplanes; ++p) split_store_chunk(v, planes + p * j.pstride + row * j.ldp + col, n, vec);
         }
         __syncthreads();
     }

@@ -15,24 +15,6 @@ namespace mm {
 
 
 // ------------------------------------------------------------------ split pass
-// Eight bfloat16 values of one plane row as one 16-byte store, or element by
-// element where the chunk is not 16-byte aligned or would pass the row end.
-typedef uint16_t u16x8_t __attribute__((ext_vector_type(8)));
-typedef float f32x4_ua __attribute__((ext_vector_type(4), aligned(4)));   // element-aligned vector load
-
-__device__ __forceinline__ void store_plane_chunk(uint16_t *dst, const uint16_t (&h)[8], int n, bool vec) {
-    if (vec && n == 8) {
-        u16x8_t v;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = h[e];
-        *reinterpret_cast<u16x8_t *>(dst) = v;
-    } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-            if (e < n) dst[e] = h[e];
-    }
-}
-
 // Row-major planes with rows of ldp >= cols elements (columns cols..ldp-1
 // written as zero): each thread splits 8 consecutive elements of one row,
 // read as two 16-byte loads when they are all inside the row (the memory
@@ -49,8 +31,7 @@ __global__ void split_rows_kernel(const float *__restrict__ X, int64_t ldx, int6
         const gptr<const float> src = (gptr<const float>)(X + r * ldx + c0);
         float v[8];
         if (c0 + 8 <= cols) {
-            const f32x4_ua lo = *(const __attribute__((address_space(1))) f32x4_ua *)src;
-            const f32x4_ua hi = *(const __attribute__((address_space(1))) f32x4_ua *)(src + 4);
+            const f32x4 lo = load_f32x4_ea(src), hi = load_f32x4_ea(src + 4);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 v[e] = lo[e];
@@ -61,15 +42,8 @@ __global__ void split_rows_kernel(const float *__restrict__ X, int64_t ldx, int6
             for (int e = 0; e < 8; ++e) v[e] = (c0 + e < cols) ? src[e] : 0.f;
         }
         const int n = ldp - c0 < 8 ? (int)(ldp - c0) : 8;
-        for (int p = 0; p < nplanes; ++p) {
-            uint16_t h[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                h[e] = split_bf16_bits(v[e]);
-                v[e] = v[e] - split_bf16_value(h[e]);
-            }
-            store_plane_chunk(planes + p * plane_stride + r * ldp + c0, h, n, vec_store);
-        }
+        for (int p = 0; p < nplanes; ++p)
+            split_store_chunk(v, (gptr<uint16_t>)(planes + p * plane_stride + r * ldp + c0), n, vec_store);
     }
 }
 
@@ -93,7 +67,7 @@ __global__ __launch_bounds__(256) void split_transpose_kernel(const float *__res
         if (r < rows) {
             const gptr<const float> src = (gptr<const float>)(X + r * ldx + c);
             if (c + 4 <= cols) {
-                const f32x4_ua q = *(const __attribute__((address_space(1))) f32x4_ua *)src;
+                const f32x4 q = load_f32x4_ea(src);
 #pragma unroll
                 for (int e = 0; e < 4; ++e) v[e] = q[e];
             } else {
@@ -116,15 +90,8 @@ __global__ __launch_bounds__(256) void split_transpose_kernel(const float *__res
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = tile[rl + e][cl];
         const int n = ldp - r < 8 ? (int)(ldp - r) : 8;
-        for (int p = 0; p < nplanes; ++p) {
-            uint16_t h[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                h[e] = split_bf16_bits(v[e]);
-                v[e] = v[e] - split_bf16_value(h[e]);
-            }
-            store_plane_chunk(planes + p * plane_stride + c * ldp + r, h, n, vec_store);
-        }
+        for (int p = 0; p < nplanes; ++p)
+            split_store_chunk(v, (gptr<uint16_t>)(planes + p * plane_stride + c * ldp + r), n, vec_store);
     }
 }
 

@@ -26,6 +26,33 @@ typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 __device__ __forceinline__ uint16_t split_bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
 __device__ __forceinline__ float split_bf16_value(uint16_t b) { return __builtin_bit_cast(float, (uint32_t)b << 16); }
 
+// Element-aligned 16-byte FP32 load (the memory system runs in unaligned
+// mode, so a vector wholly inside a row needs only element alignment).
+typedef float f32x4_ea __attribute__((ext_vector_type(4), aligned(4)));
+__device__ __forceinline__ f32x4 load_f32x4_ea(gptr<const float> p) {
+    return *reinterpret_cast<gptr<const f32x4_ea>>(p);
+}
+
+// Split v[0..7] into its next bfloat16 plane in place (v keeps the leftover)
+// and store the 8 values as one 16-byte store, or element by element where
+// the chunk is not 16-byte aligned (vec false) or only n < 8 of it is inside
+// the row.
+__device__ __forceinline__ void split_store_chunk(float (&v)[8], gptr<uint16_t> dst, int n, bool vec) {
+    u16x8 h;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        h[e] = split_bf16_bits(v[e]);
+        v[e] = v[e] - split_bf16_value(h[e]);
+    }
+    if (vec && n == 8) {
+        *reinterpret_cast<gptr<u16x8>>(dst) = h;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (e < n) dst[e] = h[e];
+    }
+}
+
 // ------------------------------------------------------------------ split GEMM
 // Plane pairs of each method; entry 0 is the leading product.
 template <int NPROD> struct SplitTerms;
