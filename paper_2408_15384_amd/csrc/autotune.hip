@@ -53,7 +53,7 @@ Key key_of(mm_method m, int64_t M, int64_t N, int64_t K) {
 // the padding of ragged edge tiles and the idle units of a small grid, which
 // is what decides between tile sizes.  Split variants that read planes are
 // also charged their plane pass: the FP32 operands read once and the planes
-// written once at 4 TB/s, plus 6 us for its two launches; fused split
+// written once at 5.5 TB/s, plus 6 us for its two launches; fused split
 // variants have no pass.
 struct Candidate {
     int variant;
@@ -83,7 +83,7 @@ int pick(const Candidate (&c)[NC], int64_t M, int64_t N, int64_t K, int planes) 
     for (size_t i = 0; i < NC; ++i) {
         const double tiles = (double)((M + c[i].bm - 1) / c[i].bm) * (double)((N + c[i].bn - 1) / c[i].bn);
         double t = std::ceil(tiles / kCUs) * 2.0 * c[i].bm * c[i].bn * k * kCUs / (c[i].rate * 1e12);
-        if (c[i].plane_pass) t += ((double)M * k + k * (double)N) * (4.0 + 2.0 * planes) / 4e12 + 6e-6;
+        if (c[i].plane_pass) t += ((double)M * k + k * (double)N) * (4.0 + 2.0 * planes) / 5.5e12 + 6e-6;
         if (i == 0 || t < best_t) {
             best = c[i].variant;
             best_t = t;
