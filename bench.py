@@ -599,8 +599,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: the product runs on a single MI355X; multi-GPU sharding is "
-              "not part of this build (use --gpus 1)", file=sys.stderr)
+        print("bench.py measures one GPU: the product runs on a single MI355X; sharding over several GPUs is "
+              "not implemented (use --gpus 1)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -16,8 +16,8 @@ GPU by the library.
 
 Methods: f64, f32, split3, split6 (bfloat16 split products, FP32 output) and
 strassen (one Winograd level on the binary64 product).  The product always
-runs in libmm's kernels; without the built library or a GPU the driver exits
-with an error.
+runs in libmm's kernels; without the built library or a GPU the command
+exits with an error.
 """
 from __future__ import annotations
 
