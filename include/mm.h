@@ -259,8 +259,10 @@ mm_status mm_grouped_plan_destroy(mm_grouped_plan *plan);
 mm_status mm_grouped_plan_launch(mm_grouped_plan *plan, void *stream);
 
 /* Tile configuration the plan chose (autotuned or default), its schedule, its
- * tile count, the workgroups of its grid (persistent grid, or one per tile for
- * schedule 3) and whether it replays a graph.  Every output is nullable. */
+ * tile count, the workgroups of its grid (persistent grid; for schedule 3 one
+ * per tile, the count rounded up to a multiple of 64 so that runs of 8
+ * consecutive tiles go to one XCD) and whether it replays a graph.  Every
+ * output is nullable. */
 mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out, int32_t *schedule_out,
                                int64_t *tiles_out, int32_t *grid_out, int32_t *uses_graph_out);
 
@@ -270,7 +272,7 @@ mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out
  * given order, a persistent grid takes tiles by a fixed stride; 1 = heaviest
  * problems (largest M*N*K) first, fixed stride; 2 = heaviest first, the
  * persistent grid pulls tiles from a device work counter; 3 = heaviest first,
- * one workgroup per tile dispatched in tile order by the hardware.  Every
+ * one workgroup per tile, dispatched by the hardware.  Every
  * schedule gives the same bits.  An existing plan must have been built with
  * the same variant and schedule.
  */
