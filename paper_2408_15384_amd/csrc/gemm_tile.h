@@ -266,9 +266,9 @@ struct TileGemm {
 // which makes every fragment read bank-conflict free.  Rows of A past M and
 // column chunks of B past N are clamped in bounds (they only feed entries of
 // C that are not stored).  It needs K % BK == 0, N, lda, ldb multiples of the
-// 16-byte vector and 16-byte aligned bases; other problems run the
-// register-staged tile (same tile shape) in the same kernel.
-typedef __attribute__((address_space(1))) void mm_gvoid;
+// 16-byte vector, 16-byte aligned bases and K slices whose lane offsets fit
+// 31 bits; other problems run the register-staged tile (same tile shape) in
+// the same kernel.
 typedef __attribute__((address_space(3))) void mm_lvoid;
 
 template <typename T, int BM_, int BN_, int BK_, int WM_, int WN_, int STAGES_>

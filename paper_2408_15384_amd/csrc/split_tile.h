@@ -283,7 +283,6 @@ struct SplitTile {
 // swizzled layout puts in its slot.  Rows past M (or N) are clamped to the
 // last row: they only feed entries of C that are not stored.  K is a
 // multiple of 32 (the planes are zero-padded), so no K-tail checks remain.
-typedef __attribute__((address_space(1))) void mm_global_void;
 typedef __attribute__((address_space(3))) void mm_lds_void;
 
 template <int NPROD, int BM_, int BN_, int WM_, int WN_, int STAGES_>
