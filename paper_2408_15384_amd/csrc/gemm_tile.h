@@ -362,6 +362,7 @@ struct TileGemmDirect {
     // stage) is issued after the first reads, off the path to the first MFMA.
     static constexpr int PER = 16 / (int)sizeof(T);
     static constexpr int CH = KS * (int)sizeof(T) / 16 > 0 ? KS * (int)sizeof(T) / 16 : 1;
+    static_assert(KS >= PER && CH * PER == KS, "a lane group's K run must be whole 16-byte A chunks");
 
     static __device__ __forceinline__ void read_sub(const T *As, const T *Bs, int s, int wm, int wn, int li, int q,
                                                     T (&a)[FM][KS], T (&b)[FN][KS]) {
