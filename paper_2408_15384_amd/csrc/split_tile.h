@@ -309,6 +309,8 @@ struct SplitTileDirect {
     static constexpr int LOADS = STAGE_CHUNKS / NT;      // load instructions per thread per stage
     static_assert(STAGE_CHUNKS % NT == 0, "stage must split evenly over the threads");
     static_assert(STAGES >= 2 && STAGES <= 4, "stages");
+    // one load instruction (64 slots = 16 rows) never straddles planes or the A/B boundary
+    static_assert(BM % 16 == 0 && BN % 16 == 0, "tile sides in whole 16-row groups");
 
     static __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 2) & 3); }
 
