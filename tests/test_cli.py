@@ -36,3 +36,15 @@ def test_inputs_follow_the_seeded_generators():
     a = cli.parse(["16", "8", "12", "--method", "f32", "--inputs", "int"])
     A, _ = cli.host_operands(a)
     assert A.dtype == np.float32 and np.all(A == np.round(A)) and np.abs(A).max() <= 8
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # one GPU only: asking for more exits with a message before touching a device
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2", "--steps", "1", "--warmup", "0"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
