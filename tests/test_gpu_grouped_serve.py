@@ -194,9 +194,9 @@ def test_autotuners(mm, tmp_path):
 METHOD_ID = {"f64": 0, "f32": 1, "split3": 2, "split6": 3}
 
 
-def serve_all(mm, reqs, budget, slots, max_batch, one_at_a_time=False):
+def serve_all(mm, reqs, budget, slots, max_batch, one_at_a_time=False, **server_kw):
     outs = []
-    with mm.Server(budget_bytes=budget, slots=slots, max_batch=max_batch) as srv:
+    with mm.Server(budget_bytes=budget, slots=slots, max_batch=max_batch, **server_kw) as srv:
         ids = []
         for method, A, B in reqs:
             C = torch.full((A.shape[0], B.shape[1]), float("nan"), dtype=DT[method], device="cuda")
@@ -249,3 +249,28 @@ def test_serving_stats(mm):
     assert 0 < st["p50_ms"] <= st["p99_ms"] <= st["max_ms"]
     assert st["useful_flop"] == 20 * 2 * 256 ** 3
     assert st["tflops"] > 0 and st["launches"] >= 1
+
+
+def test_serving_large_class_and_workspace_growth(mm):
+    """Requests of the large class (M*N >= 1024^2) with plane-reading split
+    tiles: each slot's split workspace grows several times while earlier
+    launches still run (outgrown buffers are kept, not freed).  Results equal
+    the same requests served one at a time and stay within the oracle bound."""
+    shapes = [(300, 200, 96), (1024, 1024, 64), (1040, 1100, 160), (200, 300, 500), (1100, 1030, 384),
+              (1200, 1024, 640), (700, 90, 33), (1030, 1200, 1000)]
+    methods = ["split6", "split3", "f64", "split6", "split3", "split6", "f64", "split6"]
+    reqs, hostAB = [], []
+    for i, ((M, N, K), m) in enumerate(zip(shapes, methods)):
+        A, B = I.pair(KIND[m], M, N, K, seed=(14, i))
+        hostAB.append((m, A, B))
+        reqs.append((m, torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()))
+    # large class: the 128x128 register tile for binary64, plane-reading 256x128 split tiles
+    kw = dict(variants=[-1, -1, -1, -1], variants_large=[0, -1, 14, 9], large_mn=1024 * 1024)
+    alone, _ = serve_all(mm, reqs, budget=1 << 34, slots=1, max_batch=1, one_at_a_time=True, **kw)
+    mix, st = serve_all(mm, reqs, budget=1 << 34, slots=2, max_batch=4, **kw)
+    assert st["completed"] == len(reqs) and st["failed"] == 0
+    for i in range(len(reqs)):
+        assert np.array_equal(alone[i], mix[i]), f"request {i}"
+    for i, (m, A, B) in enumerate(hostAB):
+        check_oracle(m, [(A, B)], [mix[i]], [0])
+
