@@ -88,6 +88,25 @@ def test_grouped_equals_single_every_schedule(mm, method):
     check_oracle(method, hostAB, Cs, range(len(shapes)))
 
 
+@pytest.mark.parametrize("method", ["f32", "split6"])
+def test_grouped_more_problems_than_the_staged_table(mm, method):
+    """1100 problems: past the 1024 prefix sums a persistent workgroup stages
+    in LDS, so the owner search reads global memory; every schedule still
+    equals the single-problem kernel (a 64x64 variant for the split form)."""
+    shapes = ragged_shapes(1100, 1, 48, seed=31)
+    As, Bs, Cs, hostAB = make_batch(method, shapes, seed=32)
+    variant = 1 if method == "f32" else 8
+    ref = singles(mm, method, variant, As, Bs)
+    for schedule in (0, 1, 2, 3):
+        for C in Cs:
+            C.fill_(float("nan"))
+        mm.gemm_grouped(method, As, Bs, Cs, variant=variant, schedule=schedule)
+        torch.cuda.synchronize()
+        for i, C in enumerate(Cs):
+            assert np.array_equal(C.cpu().numpy(), ref[i]), f"schedule {schedule} problem {i}"
+    check_oracle(method, hostAB, Cs, range(0, len(shapes), 50))
+
+
 @pytest.mark.parametrize("method", ["split3", "split6"])
 def test_grouped_every_split_variant(mm, method):
     # plane-reading and fused variants alike: grouped == single, bit for bit
