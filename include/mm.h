@@ -29,6 +29,8 @@
  *    writes C := 0 (an empty sum).
  *  * Leading dimensions must satisfy lda >= max(K,1), ldb >= max(N,1),
  *    ldc >= max(N,1); C must not overlap A or B.
+ *  * Every dimension is at most 2^40, and every stored matrix spans at most
+ *    2^62 elements ((rows-1)*ld + cols); larger shapes return MM_E_INVAL.
  *  * Calls on distinct streams may run concurrently from any threads.
  */
 #ifndef MM_H

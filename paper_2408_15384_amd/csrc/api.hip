@@ -84,6 +84,15 @@ static size_t span_bytes(int64_t rows, int64_t cols, int64_t ld, size_t elem) {
     return ((size_t)(rows - 1) * (size_t)ld + (size_t)cols) * elem;
 }
 
+// Largest dimension accepted, and the largest element offset a stored matrix
+// may span: byte extents then fit in 64 bits for every element size.
+constexpr int64_t kMaxDim = (int64_t)1 << 40;
+
+static bool extent_overflows(int64_t rows, int64_t cols, int64_t ld) {
+    if (rows <= 0 || cols <= 0) return false;
+    return (__int128)(rows - 1) * ld + cols > ((__int128)1 << 62);
+}
+
 mm_status check_split_k(int64_t K) {
     if (K > kSplitMaxK) return fail(MM_E_UNSUPPORTED, "split methods take K <= 2^26 - 32");
     return MM_OK;
@@ -92,16 +101,14 @@ mm_status check_split_k(int64_t K) {
 mm_status check_gemm_args(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
                           int64_t ldb, const void *C, int64_t ldc, size_t ab_elem, size_t c_elem) {
     if (M < 0 || N < 0 || K < 0) return fail(MM_E_INVAL, "negative dimension");
-    const int64_t LIM = (int64_t)1 << 40;
-    if (M > LIM || N > LIM || K > LIM) return fail(MM_E_INVAL, "dimension too large");
+    if (M > kMaxDim || N > kMaxDim || K > kMaxDim) return fail(MM_E_INVAL, "dimension too large");
     if (lda < (K > 1 ? K : 1)) return fail(MM_E_INVAL, "lda < max(K,1)");
     if (ldb < (N > 1 ? N : 1)) return fail(MM_E_INVAL, "ldb < max(N,1)");
     if (ldc < (N > 1 ? N : 1)) return fail(MM_E_INVAL, "ldc < max(N,1)");
     if (M == 0 || N == 0) return MM_OK;
     if (!C) return fail(MM_E_INVAL, "C is NULL");
     if (K > 0 && (!A || !B)) return fail(MM_E_INVAL, "A or B is NULL");
-    if ((__int128)(M - 1) * ldc + N > ((__int128)1 << 62) || (__int128)(M - 1) * lda + K > ((__int128)1 << 62) ||
-        (__int128)(K > 0 ? K - 1 : 0) * ldb + N > ((__int128)1 << 62))
+    if (extent_overflows(M, N, ldc) || extent_overflows(M, K, lda) || extent_overflows(K, N, ldb))
         return fail(MM_E_INVAL, "matrix extent overflows");
     const size_t cb = span_bytes(M, N, ldc, c_elem);
     if (K > 0 && (overlaps(C, cb, A, span_bytes(M, K, lda, ab_elem)) || overlaps(C, cb, B, span_bytes(K, N, ldb, ab_elem))))
@@ -182,10 +189,14 @@ mm_status mm_split_bf16(int64_t rows, int64_t cols, const float *X, int64_t ldx,
                         uint16_t *planes, int64_t plane_stride, void *stream) {
     MM_GUARD_BEGIN
     if (rows < 0 || cols < 0) return fail(MM_E_INVAL, "negative dimension");
+    if (rows > kMaxDim || cols > kMaxDim) return fail(MM_E_INVAL, "dimension too large");
     if (nplanes < 1 || nplanes > 3) return fail(MM_E_INVAL, "nplanes must be 1, 2 or 3");
     if (ldx < (cols > 1 ? cols : 1)) return fail(MM_E_INVAL, "ldx < max(cols,1)");
     if (rows == 0 || cols == 0) return MM_OK;
     if (!X || !planes) return fail(MM_E_INVAL, "NULL pointer");
+    if (extent_overflows(rows, cols, ldx) || (__int128)rows * cols > ((__int128)1 << 60) ||
+        plane_stride > ((int64_t)1 << 60))
+        return fail(MM_E_INVAL, "matrix extent overflows");
     if (plane_stride < rows * cols) return fail(MM_E_INVAL, "plane_stride < rows*cols");
     if (overlaps(X, span_bytes(rows, cols, ldx, 4), planes, (size_t)plane_stride * nplanes * 2))
         return fail(MM_E_INVAL, "planes overlap X");
@@ -264,6 +275,7 @@ mm_status mm_gemm_ex(mm_method method, mm_op opa, mm_op opb, int64_t M, int64_t 
     if (method < MM_F64 || method > MM_SPLIT_BF16_6) return fail(MM_E_INVAL, "unknown method");
     const size_t e = method == MM_F64 ? 8 : 4;
     if (M < 0 || N < 0 || K < 0) return fail(MM_E_INVAL, "negative dimension");
+    if (M > kMaxDim || N > kMaxDim || K > kMaxDim) return fail(MM_E_INVAL, "dimension too large");
     // stored shapes: A is (M x K) or (K x M), B is (K x N) or (N x K)
     const int64_t ar = opa ? K : M, ac = opa ? M : K, br = opb ? N : K, bc = opb ? K : N;
     if (lda < (ac > 1 ? ac : 1)) return fail(MM_E_INVAL, "lda smaller than a stored row of A");
@@ -272,6 +284,8 @@ mm_status mm_gemm_ex(mm_method method, mm_op opa, mm_op opb, int64_t M, int64_t 
     if (M == 0 || N == 0) return MM_OK;
     if (!C) return fail(MM_E_INVAL, "C is NULL");
     if (K > 0 && (!A || !B)) return fail(MM_E_INVAL, "A or B is NULL");
+    if (extent_overflows(M, N, ldc) || extent_overflows(ar, ac, lda) || extent_overflows(br, bc, ldb))
+        return fail(MM_E_INVAL, "matrix extent overflows");
     const size_t cb = span_bytes(M, N, ldc, e);
     if (K > 0 && (overlaps(C, cb, A, span_bytes(ar, ac, lda, e)) || overlaps(C, cb, B, span_bytes(br, bc, ldb, e))))
         return fail(MM_E_INVAL, "C overlaps A or B");
@@ -378,8 +392,11 @@ mm_status mm_residual_f64(int64_t M, int64_t N, int64_t K, const void *A, int64_
     if ((in_dtype != 0 && in_dtype != 1) || (c_dtype != 0 && c_dtype != 1))
         return fail(MM_E_INVAL, "dtype must be 0 (binary64) or 1 (FP32)");
     if (M < 0 || N < 0 || K < 0) return fail(MM_E_INVAL, "negative dimension");
+    if (M > kMaxDim || N > kMaxDim || K > kMaxDim) return fail(MM_E_INVAL, "dimension too large");
     if (lda < (K > 1 ? K : 1) || ldb < (N > 1 ? N : 1) || ldc < (N > 1 ? N : 1))
         return fail(MM_E_INVAL, "leading dimension too small");
+    if (extent_overflows(M, N, ldc) || extent_overflows(M, K, lda) || extent_overflows(K, N, ldb))
+        return fail(MM_E_INVAL, "matrix extent overflows");
     if (!out) return fail(MM_E_INVAL, "out is NULL");
     if ((M > 0 && K > 0 && !A) || (K > 0 && N > 0 && !B) || (M > 0 && N > 0 && !C) || (N > 0 && !x))
         return fail(MM_E_INVAL, "NULL operand");

@@ -227,6 +227,14 @@ static mm_status launch(mm_server *s, Slot &slot, const std::vector<uint64_t> &i
     return MM_OK;
 }
 
+// A launch that failed part-way may have left copies and kernels on the slot's
+// stream that still read its pinned staging and the requests' operands: drain
+// the stream before the slot and the requests are released.
+static void finish_failed(mm_server *s, Slot &slot, mm_status st) {
+    if (s->dry_tflops <= 0 && slot.stream) (void)hipStreamSynchronize(slot.stream);
+    finish(s, slot, st);
+}
+
 static void scheduler_main(mm_server *s) {
     if (s->dry_tflops <= 0) (void)hipSetDevice(s->cfg.device);
     std::unique_lock<std::mutex> lock(s->mu);
@@ -257,8 +265,13 @@ static void scheduler_main(mm_server *s) {
             if (batch.empty()) break;
             s->in_flight_bytes = bytes;
             if (bytes > s->peak_bytes) s->peak_bytes = bytes;
-            const mm_status st = launch(s, slot, batch);
-            if (st != MM_OK) finish(s, slot, st);
+            mm_status st;
+            try {
+                st = launch(s, slot, batch);
+            } catch (...) {  // host allocation failure while packing the batch
+                st = MM_E_NOMEM;
+            }
+            if (st != MM_OK) finish_failed(s, slot, st);
         }
         bool any_busy = false;
         for (Slot &slot : s->slots) any_busy = any_busy || slot.busy;
@@ -379,14 +392,21 @@ mm_status mm_serve_wait(mm_server *s, uint64_t id, int64_t timeout_us, mm_status
     try {
         if (!s) return fail(MM_E_INVAL, "NULL server");
         std::unique_lock<std::mutex> lock(s->mu);
-        auto it = s->reqs.find(id);
-        if (it == s->reqs.end()) return fail(MM_E_INVAL, "unknown request id (or already waited for)");
-        auto ready = [&] { return s->reqs[id].done; };
+        if (s->reqs.find(id) == s->reqs.end()) return fail(MM_E_INVAL, "unknown request id (or already waited for)");
+        // A request leaves the table when its first waiter collects it; another
+        // thread waiting on the same id then wakes and reports it as unknown.
+        auto ready = [&] {
+            auto it = s->reqs.find(id);
+            return it == s->reqs.end() || it->second.done;
+        };
         if (timeout_us < 0) s->cv_done.wait(lock, ready);
         else if (!s->cv_done.wait_for(lock, std::chrono::microseconds(timeout_us), ready))
             return fail(MM_E_TIMEOUT, "request still pending");
-        const Request r = s->reqs[id];
-        s->reqs.erase(id);
+        auto it = s->reqs.find(id);
+        if (it == s->reqs.end()) return fail(MM_E_INVAL, "request already collected by another waiter");
+        const Request r = it->second;
+        s->reqs.erase(it);
+        s->cv_done.notify_all();
         if (req_status) *req_status = r.status;
         if (latency_ms) *latency_ms = r.latency_ms;
         return MM_OK;

@@ -76,6 +76,29 @@ def test_invalid_arguments_without_gpu(lib):
     assert lib.mm_gemm_grouped_config(probs, 0, api.MM_F64, 0, 3, None, None) == api.MM_OK
 
 
+def test_extent_overflow_rejected_by_every_product_entry_point(lib):
+    # a leading dimension that makes (rows-1)*ld + cols exceed 2^62 elements
+    # is refused before any device work, transposed layouts and the residual
+    # probe included (the addresses are never dereferenced)
+    a, b, c, x = 1 << 40, 1 << 41, 1 << 42, 1 << 43
+    huge = 1 << 61
+    E = api.MM_E_INVAL
+    assert lib.mm_gemm_f64(8, 2, 2, a, huge, b, 2, c, 2, None) == E
+    assert b"overflow" in lib.mm_last_error()
+    for m in (api.MM_F64, api.MM_F32, api.MM_SPLIT_BF16_6):
+        # A stored transposed: K x M rows of length M, ld huge
+        assert lib.mm_gemm_ex(m, 1, 0, 2, 2, 8, a, huge, b, 2, c, 2, None, 0, None) == E
+        assert b"overflow" in lib.mm_last_error()
+        # B stored transposed: N x K
+        assert lib.mm_gemm_ex(m, 0, 1, 2, 8, 2, a, 2, b, huge, c, 8, None, 0, None) == E
+    assert lib.mm_gemm_ex(api.MM_F64, 0, 0, 2, 2, (1 << 40) + 1, a, (1 << 40) + 1, b, 2, c, 2, None, 0, None) == E
+    out = ctypes.c_double()
+    assert lib.mm_residual_f64(8, 2, 2, a, 2, b, 2, c, huge, 0, 0, x, ctypes.byref(out), None, 0, None) == E
+    assert b"overflow" in lib.mm_last_error()
+    assert lib.mm_split_bf16(8, 2, a, huge, 2, 0, b, 16, None) == E
+    assert lib.mm_split_bf16(1 << 31, 1 << 31, a, 1 << 31, 2, 0, b, 1 << 62, None) == E
+
+
 def test_split_k_limit_without_gpu(lib):
     # the split tiles address 16 plane rows with 32-bit byte offsets: K above
     # 2^26 - 32 is refused by every entry point that takes a split method,

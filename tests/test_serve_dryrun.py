@@ -161,6 +161,33 @@ def test_wait_timeout_and_unknown_id():
         srv.close()
 
 
+def test_two_waiters_on_one_request():
+    # both threads block in the library (ctypes releases the GIL): the first
+    # to wake collects the request, the other reports it unknown and returns
+    import threading
+    srv = api.Server(budget_bytes=1 << 40, slots=1, max_batch=1, dry_run_tflops=1e-4)
+    try:
+        r = submit(srv, 0, 256, 256, 256)           # ~0.3 s on the model
+        out = []
+
+        def waiter():
+            try:
+                out.append(srv.wait(r, timeout_us=20_000_000)[0])
+            except api.MMError as e:
+                out.append(e.status)
+
+        ts = [threading.Thread(target=waiter) for _ in range(2)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join(30)
+        assert not any(t.is_alive() for t in ts)
+        assert sorted(out) == sorted([api.MM_OK, api.MM_E_INVAL])
+        assert srv.stats()["completed"] == 1
+    finally:
+        srv.close()
+
+
 def test_invalid_requests_rejected():
     srv = api.Server(budget_bytes=1 << 40, slots=1, max_batch=1, dry_run_tflops=1.0)
     try:
