@@ -245,10 +245,15 @@ typedef struct mm_grouped_plan mm_grouped_plan;
  *     launch, stream-ordered).  Otherwise *plan_inout is a plan cache: if it is
  *     NULL a plan is built for these shapes (tile map, device descriptor
  *     buffers, split workspace, and a HIP graph of the whole sequence captured
- *     on `stream`) and returned; if it is an existing plan whose shapes match,
- *     only the operand pointers are refreshed and the graph is replayed.  A
- *     plan whose shapes differ is MM_E_INVAL.  A plan is owned by the caller
- *     and freed with mm_grouped_plan_destroy after its last launch finished.
+ *     on a stream of the plan's own) and returned; if it is an existing plan
+ *     whose shapes match, only the operand pointers are refreshed and the
+ *     graph is replayed on `stream`.  A plan whose shapes differ is
+ *     MM_E_INVAL.  A plan holds one set of device descriptors: its launches
+ *     are ordered by the stream they are enqueued on, and a caller using one
+ *     plan from several streams orders those streams itself.  For split
+ *     methods a refresh also waits for `stream` to drain (the split jobs are
+ *     copied from host memory).  A plan is owned by the caller and freed with
+ *     mm_grouped_plan_destroy after its last launch finished.
  * count == 0 is a no-op.  Problems with M == 0 or N == 0 are skipped.
  */
 mm_status mm_gemm_grouped(const mm_problem *probs, int32_t count, mm_method method,

@@ -63,7 +63,7 @@ void retain_default_pool() {
     done.push_back(dev);
 }
 
-static mm_status check_arch() {
+mm_status check_arch() {
     DeviceInfo d;
     mm_status s = device_info(&d);
     if (s != MM_OK) return s;

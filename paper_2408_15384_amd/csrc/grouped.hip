@@ -591,6 +591,7 @@ mm_status mm_gemm_grouped(const mm_problem *probs, int32_t count, mm_method meth
             return run_plan(p, probs, st, true);
         }
         if (count == 0) return MM_OK;
+        if ((s = check_arch()) != MM_OK) return s;
         int schedule = 0;
         const int variant = select_grouped(probs, count, method, &schedule);
         if (!plan_inout) return run_once(probs, count, method, variant, schedule, st);
@@ -657,6 +658,7 @@ mm_status mm_gemm_grouped_config(const mm_problem *probs, int32_t count, mm_meth
             return run_plan(p, probs, st, true);
         }
         if (count == 0) return MM_OK;
+        if ((s = check_arch()) != MM_OK) return s;
         if (!plan_inout) return run_once(probs, count, method, variant, schedule, st);
         mm_grouped_plan *p = nullptr;
         s = create_plan(probs, count, method, variant, schedule, &p);

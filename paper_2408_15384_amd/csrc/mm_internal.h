@@ -19,6 +19,8 @@ mm_status hip_fail(hipError_t e, const char *what);
 // the 32-bit per-lane offsets of a ring load over 16 plane rows fit.
 constexpr int64_t kSplitMaxK = ((int64_t)1 << 26) - 32;
 mm_status check_split_k(int64_t K);
+// The current device is one the kernels were built for (gfx950).
+mm_status check_arch();
 mm_status check_gemm_args(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
                           int64_t ldb, const void *C, int64_t ldc, size_t ab_elem, size_t c_elem);
 

@@ -333,7 +333,13 @@ mm_status mm_serve_create(const mm_serve_config *cfg, mm_server **out) {
         s->slots.resize(cfg->slots);
         if (s->dry_tflops <= 0) {
             hipError_t e = hipSetDevice(cfg->device);
-            if (e == hipSuccess) retain_default_pool();
+            if (e == hipSuccess) {
+                const mm_status as = check_arch();
+                if (as != MM_OK) {
+                    release(s);
+                    return as;
+                }
+            }
             const size_t cap = cfg->max_batch;
             for (Slot &slot : s->slots) {
                 if (e == hipSuccess) e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
