@@ -412,7 +412,10 @@ mm_status mm_serve_submit(mm_server *srv, const mm_problem *req, mm_method metho
 
 /* Wait up to timeout_us (negative: forever) for request id.  On MM_OK the
  * request has finished: *req_status (nullable) is its own status and
- * *latency_ms (nullable) its latency.  MM_E_TIMEOUT if still pending. */
+ * *latency_ms (nullable) its latency, and the id is retired.  MM_E_TIMEOUT if
+ * still pending (the id stays valid).  An id that was never issued or is
+ * already retired is MM_E_INVAL; of several threads waiting on one id, the
+ * first to wake collects it and the others return MM_E_INVAL. */
 mm_status mm_serve_wait(mm_server *srv, uint64_t id, int64_t timeout_us,
                         mm_status *req_status, double *latency_ms);
 
