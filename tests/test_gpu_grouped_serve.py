@@ -161,6 +161,36 @@ def test_plan_graph_replay(mm, method):
     del junk
 
 
+@pytest.mark.parametrize("method,variant", [("f32", 1), ("split3", 8)])
+@pytest.mark.parametrize("schedule", [0, 2, 3])
+def test_plan_replay_every_schedule(mm, method, variant, schedule):
+    """A plan's graph holds [split pass ->] counter reset -> grouped product;
+    replayed several times with eager work and synchronisation in between,
+    every replay equals the single-problem kernel (schedule 2 depends on the
+    in-graph reset of its work counter; variant 8 reads planes, so the split
+    pass is in the graph too)."""
+    shapes = ragged_shapes(30, 4, 200, seed=41)
+    As, Bs, Cs, _ = make_batch(method, shapes, seed=42)
+    ref = singles(mm, method, variant, As, Bs)
+    plan = mm.GroupedPlan(method, variant=variant, schedule=schedule)
+    try:
+        plan.run(As, Bs, Cs)
+        assert plan.info()["graph"] and plan.info()["schedule"] == schedule
+        for rep in range(4):
+            for C in Cs:
+                C.fill_(float("nan"))
+            junk = torch.randn(256, 256, device="cuda").sum()
+            torch.cuda.synchronize()
+            plan.replay()
+            torch.cuda.synchronize()
+            for i, C in enumerate(Cs):
+                assert np.array_equal(C.cpu().numpy(), ref[i]), f"replay {rep} problem {i}"
+            del junk
+    finally:
+        torch.cuda.synchronize()
+        plan.close()
+
+
 def test_grouped_config4_shapes_sampled(mm):
     shapes = [tuple(int(x) for x in s) for s in I.grouped_shapes(512, 32, 1024, seed=0)]
     As, Bs, Cs, hostAB = make_batch("f32", shapes, seed=0)
