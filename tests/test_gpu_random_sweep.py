@@ -1,0 +1,93 @@
+"""Seeded random sweep through the C ABI: each case draws a method, a tile
+variant (or a transposition of either operand), the three sizes, and for every
+operand a padded leading dimension and an element offset into its allocation.
+Padding holds NaN, so a kernel that touched an element outside its matrix
+would show it.  Every result is checked against the oracle: the per-entry
+bound of the sum for binary64 and FP32, the bfloat16 plane emulation for the
+split methods, and bit equality on integer inputs for every method."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2408_15384_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+METHODS = ("f64", "f32", "split3", "split6")
+CASES = 160
+
+
+@pytest.fixture(scope="module")
+def mm():
+    from paper_2408_15384_amd import api
+    api.load_library()
+    assert api.lib().mm_init(0) == 0, api.lib().mm_last_error()
+    return api
+
+
+def stored(host, pad, off, dtype):
+    """Device copy of a row-major host matrix with leading dimension
+    cols + pad, starting `off` elements into a NaN-filled allocation."""
+    r, c = host.shape
+    ld = c + pad
+    buf = torch.full((off + r * ld + 16,), float("nan"), dtype=dtype, device="cuda")
+    view = buf.as_strided((r, c), (ld, 1), off)
+    view.copy_(torch.from_numpy(np.ascontiguousarray(host)).to(dtype))
+    return view, buf
+
+
+def draw_case(i):
+    rng = np.random.default_rng((2024, i))
+    method = METHODS[i % 4]
+    M, N, K = (int(x) for x in I.log_uniform_dims(rng, 3, 1, 700))
+    integer = rng.random() < 0.25
+    transposed = rng.random() < 0.3
+    opa = "T" if transposed and rng.random() < 0.5 else "N"
+    opb = "T" if transposed and (opa == "N" or rng.random() < 0.5) else "N"
+    pads = [int(rng.integers(0, 8)) for _ in range(3)]
+    offs = [int(rng.integers(0, 4)) for _ in range(3)]
+    vpick = int(rng.integers(0, 1 << 30))
+    return method, M, N, K, integer, opa, opb, pads, offs, vpick
+
+
+@pytest.mark.parametrize("i", range(CASES))
+def test_random_case(mm, i):
+    method, M, N, K, integer, opa, opb, pads, offs, vpick = draw_case(i)
+    f64 = method == "f64"
+    kind = ("int_f64" if f64 else "int_f32") if integer else ("uniform_f64" if f64 else "uniform_f32")
+    A, B = I.pair(kind, M, N, K, seed=(2025, i))
+    dt = torch.float64 if f64 else torch.float32
+    Ad, _ = stored(A.T if opa == "T" else A, pads[0], offs[0], dt)
+    Bd, _ = stored(B.T if opb == "T" else B, pads[1], offs[1], dt)
+    Cd, Cbuf = stored(np.zeros((M, N)), pads[2], offs[2], dt)
+    Cd.fill_(float("nan"))
+    if opa == "N" and opb == "N":
+        variant = vpick % mm.variant_count(method)
+        mm.gemm_variant(method, variant, Ad, Bd, Cd)
+        label = f"{method} v{variant}"
+    else:
+        mm.gemm_ex(method, Ad, Bd, opa, opb, C=Cd)
+        label = f"{method} {opa}{opb}"
+    torch.cuda.synchronize()
+    C = Cd.cpu().numpy()
+    case = f"case {i}: {label} M={M} N={N} K={K} pads={pads} offs={offs} integer={integer}"
+    # C's padding and the rest of its allocation are untouched
+    whole = Cbuf.cpu().numpy()
+    mask = np.ones(whole.shape, bool)
+    ld = N + pads[2]
+    for r in range(M):
+        mask[offs[2] + r * ld: offs[2] + r * ld + N] = False
+    assert np.all(np.isnan(whole[mask])), case + ": wrote outside C"
+    if integer:
+        R = oracle.gemm(A, B)
+        assert np.array_equal(C.astype(np.float64), R), case
+        return
+    if method in ("split3", "split6"):
+        R = oracle.split_product(A, B, int(method[-1]))
+        bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F32) + 2.0 ** -24 * np.abs(R)
+    else:
+        R = oracle.gemm(A, B)
+        bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F64 if f64 else oracle.U_F32)
+    assert np.all(np.isfinite(C)), case + ": non-finite result"
+    assert np.all(np.abs(C.astype(np.float64) - R) <= bound), case
