@@ -91,3 +91,58 @@ def test_random_case(mm, i):
         bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F64 if f64 else oracle.U_F32)
     assert np.all(np.isfinite(C)), case + ": non-finite result"
     assert np.all(np.abs(C.astype(np.float64) - R) <= bound), case
+
+
+GROUPED_CASES = 16
+
+
+@pytest.mark.parametrize("i", range(GROUPED_CASES))
+def test_random_grouped(mm, i):
+    """A random batch (1-40 problems, sizes 1-300, padded and offset operands)
+    under a random variant and schedule: each result equals the single-problem
+    kernel of that variant bit for bit, stays within the oracle bound, and
+    nothing outside the C matrices is written."""
+    rng = np.random.default_rng((2026, i))
+    method = METHODS[i % 4]
+    variant = int(rng.integers(0, mm.variant_count(method)))
+    schedule = int(rng.integers(0, 4))
+    count = int(rng.integers(1, 41))
+    f64 = method == "f64"
+    dt = torch.float64 if f64 else torch.float32
+    As, Bs, Cs, Cbufs, host, lay = [], [], [], [], [], []
+    for j in range(count):
+        M, N, K = (int(x) for x in I.log_uniform_dims(rng, 3, 1, 300))
+        A, B = I.pair("uniform_f64" if f64 else "uniform_f32", M, N, K, seed=(2027, i, j))
+        pads = [int(rng.integers(0, 8)) for _ in range(3)]
+        offs = [int(rng.integers(0, 4)) for _ in range(3)]
+        Ad, _ = stored(A, pads[0], offs[0], dt)
+        Bd, _ = stored(B, pads[1], offs[1], dt)
+        Cd, Cbuf = stored(np.zeros((M, N)), pads[2], offs[2], dt)
+        Cd.fill_(float("nan"))
+        As.append(Ad), Bs.append(Bd), Cs.append(Cd), Cbufs.append(Cbuf), host.append((A, B)), lay.append((pads, offs))
+    mm.gemm_grouped(method, As, Bs, Cs, variant=variant, schedule=schedule)
+    torch.cuda.synchronize()
+    for j in range(count):
+        A, B = host[j]
+        M, K = A.shape
+        N = B.shape[1]
+        pads, offs = lay[j]
+        case = f"case {i}: {method} v{variant} s{schedule} problem {j}/{count} M={M} N={N} K={K} pads={pads} offs={offs}"
+        ref = torch.full((M, N), float("nan"), dtype=dt, device="cuda")
+        mm.gemm_variant(method, variant, As[j], Bs[j], ref)
+        torch.cuda.synchronize()
+        C = Cs[j].cpu().numpy()
+        assert np.array_equal(C, ref.cpu().numpy()), case + ": differs from the single-problem kernel"
+        whole = Cbufs[j].cpu().numpy()
+        mask = np.ones(whole.shape, bool)
+        ld = N + pads[2]
+        for r in range(M):
+            mask[offs[2] + r * ld: offs[2] + r * ld + N] = False
+        assert np.all(np.isnan(whole[mask])), case + ": wrote outside C"
+        if method in ("split3", "split6"):
+            R = oracle.split_product(A, B, int(method[-1]))
+            bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F32) + 2.0 ** -24 * np.abs(R)
+        else:
+            R = oracle.gemm(A, B)
+            bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F64 if f64 else oracle.U_F32)
+        assert np.all(np.abs(C.astype(np.float64) - R) <= bound), case
