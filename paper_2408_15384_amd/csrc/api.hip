@@ -202,7 +202,7 @@ mm_status mm_split_bf16(int64_t rows, int64_t cols, const float *X, int64_t ldx,
         return fail(MM_E_INVAL, "planes overlap X");
     mm_status s = check_arch();
     if (s != MM_OK) return s;
-    MM_HIP(launch_split(rows, cols, X, ldx, nplanes, transpose, planes, plane_stride, transpose ? rows : cols,
+    MM_HIP(launch_split(rows, cols, X, ldx, nplanes, transpose, planes, plane_stride, transpose ? rows : cols, 0,
                         (hipStream_t)stream));
     return MM_OK;
     MM_GUARD_END

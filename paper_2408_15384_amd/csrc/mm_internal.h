@@ -65,16 +65,23 @@ hipError_t launch_gemm_f32(int variant, int64_t M, int64_t N, int64_t K, const f
 
 // Split pass: FP32 -> nplanes bfloat16 planes (optionally transposed); output
 // rows hold ldp elements (>= the row length), the tail written as zero.
+// interleave != 0 (ldp a multiple of 32): one array of rows of nplanes * ldp
+// elements, each 32-element block of a row followed by the same block of the
+// next plane; plane_stride is then unused.
 hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx, int nplanes, int transpose,
-                        uint16_t *planes, int64_t plane_stride, int64_t ldp, hipStream_t stream);
+                        uint16_t *planes, int64_t plane_stride, int64_t ldp, int interleave, hipStream_t stream);
 // Row length of the planes the split GEMM reads: K rounded up to 32.
 int64_t split_padded_k(int64_t K);
 
 // Split GEMM on planes: A planes M x K row-major (stride M*K), B planes stored
 // transposed N x K (stride N*K), K already padded (split_padded_k); C FP32 or
-// binary64.
+// binary64.  Planes interleaved (launch_split's layout) when
+// split_planes_interleaved(variant, nprod).
 hipError_t launch_gemm_split(int variant, int nprod, int64_t M, int64_t N, int64_t K, const uint16_t *Ap,
                              const uint16_t *Bt, void *C, int64_t ldc, int c_is_f64, hipStream_t stream);
+// Whether the single-problem split tile of this variant reads interleaved
+// planes (the direct tiles of the 2-plane method).
+bool split_planes_interleaved(int variant, int nprod);
 
 size_t split_workspace_bytes(int64_t M, int64_t N, int64_t K, int nprod);
 // Byte offset of the B planes inside the split workspace.

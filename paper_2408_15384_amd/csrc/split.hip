@@ -15,13 +15,23 @@ namespace mm {
 
 
 // ------------------------------------------------------------------ split pass
+// Element offset of (row r, column c) of plane p: separate planes (plane p at
+// p * plane_stride, rows of ldp), or interleaved (rows of nplanes * ldp; each
+// 32-column block of plane 0, then the same block of plane 1 ...).  The 8
+// columns c0 .. c0+7 (c0 a multiple of 8) are contiguous either way.
+__device__ __forceinline__ int64_t plane_offset(int interleave, int nplanes, int64_t plane_stride, int64_t ldp, int p,
+                                                int64_t r, int64_t c) {
+    return interleave ? r * nplanes * ldp + (c >> 5) * (32 * nplanes) + p * 32 + (c & 31)
+                      : p * plane_stride + r * ldp + c;
+}
+
 // Row-major planes with rows of ldp >= cols elements (columns cols..ldp-1
 // written as zero): each thread splits 8 consecutive elements of one row,
 // read as two 16-byte loads when they are all inside the row (the memory
 // system runs in unaligned mode, so element alignment suffices) and written
 // as one 16-byte store per plane.
 __global__ void split_rows_kernel(const float *__restrict__ X, int64_t ldx, int64_t rows, int64_t cols, int nplanes,
-                                  uint16_t *__restrict__ planes, int64_t plane_stride, int64_t ldp) {
+                                  uint16_t *__restrict__ planes, int64_t plane_stride, int64_t ldp, int interleave) {
     const int64_t chunks_per_row = (ldp + 7) / 8;
     const int64_t total = rows * chunks_per_row;
     const bool vec_store = ldp % 8 == 0 && plane_stride % 8 == 0 && (uintptr_t)planes % 16 == 0;
@@ -43,7 +53,8 @@ __global__ void split_rows_kernel(const float *__restrict__ X, int64_t ldx, int6
         }
         const int n = ldp - c0 < 8 ? (int)(ldp - c0) : 8;
         for (int p = 0; p < nplanes; ++p)
-            split_store_chunk(v, (gptr<uint16_t>)(planes + p * plane_stride + r * ldp + c0), n, vec_store);
+            split_store_chunk(v, (gptr<uint16_t>)(planes + plane_offset(interleave, nplanes, plane_stride, ldp, p, r, c0)),
+                              n, vec_store);
     }
 }
 
@@ -53,7 +64,7 @@ __global__ void split_rows_kernel(const float *__restrict__ X, int64_t ldx, int6
 // and plane.
 __global__ __launch_bounds__(256) void split_transpose_kernel(const float *__restrict__ X, int64_t ldx, int64_t rows,
                                                               int64_t cols, int nplanes, uint16_t *__restrict__ planes,
-                                                              int64_t plane_stride, int64_t ldp) {
+                                                              int64_t plane_stride, int64_t ldp, int interleave) {
     __shared__ float tile[64][65];
     const int64_t tiles_c = (cols + 63) / 64;
     const int64_t r0 = (blockIdx.x / tiles_c) * 64;
@@ -91,25 +102,27 @@ __global__ __launch_bounds__(256) void split_transpose_kernel(const float *__res
         for (int e = 0; e < 8; ++e) v[e] = tile[rl + e][cl];
         const int n = ldp - r < 8 ? (int)(ldp - r) : 8;
         for (int p = 0; p < nplanes; ++p)
-            split_store_chunk(v, (gptr<uint16_t>)(planes + p * plane_stride + c * ldp + r), n, vec_store);
+            split_store_chunk(v, (gptr<uint16_t>)(planes + plane_offset(interleave, nplanes, plane_stride, ldp, p, c, r)),
+                              n, vec_store);
     }
 }
 
 hipError_t launch_split(int64_t rows, int64_t cols, const float *X, int64_t ldx, int nplanes, int transpose,
-                        uint16_t *planes, int64_t plane_stride, int64_t ldp, hipStream_t stream) {
+                        uint16_t *planes, int64_t plane_stride, int64_t ldp, int interleave, hipStream_t stream) {
     if (rows <= 0 || cols <= 0) return hipSuccess;
+    if (interleave && ldp % 32 != 0) return hipErrorInvalidValue;
     if (transpose) {
         // 64-row tiles cover ldp: ldp <= round_up(rows, 64)
         const int64_t blocks = ((rows + 63) / 64) * ((cols + 63) / 64);
         if (blocks > 0x7fffffffLL || ldp < rows || ldp > (rows + 63) / 64 * 64) return hipErrorInvalidConfiguration;
         hipLaunchKernelGGL(split_transpose_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, X, ldx, rows, cols,
-                           nplanes, planes, plane_stride, ldp);
+                           nplanes, planes, plane_stride, ldp, interleave);
     } else {
         if (ldp < cols) return hipErrorInvalidConfiguration;
         int64_t blocks = (rows * ((ldp + 7) / 8) + 255) / 256;
         if (blocks > 1 << 20) blocks = 1 << 20;
         hipLaunchKernelGGL(split_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, X, ldx, rows, cols,
-                           nplanes, planes, plane_stride, ldp);
+                           nplanes, planes, plane_stride, ldp, interleave);
     }
     return hipGetLastError();
 }
@@ -127,15 +140,16 @@ hipError_t launch_split_product(int variant, int nprod, int opa, int opb, int64_
     }
     const int np = nprod == 3 ? 2 : 3;
     const int64_t Kp = split_padded_k(K);
+    const int il = split_planes_interleaved(variant, nprod);
     uint16_t *Ap = (uint16_t *)ws;
     uint16_t *Bt = (uint16_t *)((char *)ws + split_b_offset_bytes(M, K, nprod));
     // A planes are M x Kp: rows of A as stored (N), or the transpose of K x M (T)
-    hipError_t e = opa ? launch_split(K, M, A, lda, np, 1, Ap, M * Kp, Kp, st)
-                       : launch_split(M, K, A, lda, np, 0, Ap, M * Kp, Kp, st);
+    hipError_t e = opa ? launch_split(K, M, A, lda, np, 1, Ap, M * Kp, Kp, il, st)
+                       : launch_split(M, K, A, lda, np, 0, Ap, M * Kp, Kp, il, st);
     // B planes are N x Kp: the transpose of K x N (N), or rows of B as stored (T)
     if (e == hipSuccess)
-        e = opb ? launch_split(N, K, B, ldb, np, 0, Bt, N * Kp, Kp, st)
-                : launch_split(K, N, B, ldb, np, 1, Bt, N * Kp, Kp, st);
+        e = opb ? launch_split(N, K, B, ldb, np, 0, Bt, N * Kp, Kp, il, st)
+                : launch_split(K, N, B, ldb, np, 1, Bt, N * Kp, Kp, il, st);
     if (e == hipSuccess) e = launch_gemm_split(variant, nprod, M, N, Kp, Ap, Bt, C, ldc, c_is_f64, st);
     return e;
 }
@@ -216,6 +230,12 @@ bool split_variant_fused(int v) {
     switch (v) { MM_SPLIT_VARIANTS(MM_S_FUSED) default: return false; }
 }
 
+#define MM_S_DIRECT(id, bm, bn, bk, wm, wn, st) case id: return (st) >= 10 && (st) < 20;
+bool split_planes_interleaved(int v, int nprod) {
+    if (nprod != 3) return false;
+    switch (v) { MM_SPLIT_VARIANTS(MM_S_DIRECT) default: return false; }
+}
+
 #define MM_S_FLAUNCH(id, bm, bn, bk, wm, wn, st)                                                                  \
     case id:                                                                                                       \
         return nprod == 3 ? launch_fused_tile<SplitTileSel<3, bm, bn, bk, wm, wn, st>::type>(M, N, K, A, lda, B,     \
@@ -243,7 +263,7 @@ TileCfg split_variant(int v) {
 #define MM_S_LAUNCH(id, bm, bn, bk, wm, wn, st)                                                                   \
     case id:                                                                                                       \
         return nprod == 3                                                                                          \
-                   ? launch_split_tile<SplitTileSel<3, bm, bn, bk, wm, wn, st>::type>(M, N, K, Ap, Bt, C, ldc,       \
+                   ? launch_split_tile<SplitTileSel<3, bm, bn, bk, wm, wn, st, true>::type>(M, N, K, Ap, Bt, C, ldc, \
                                                                                        c_is_f64, stream)            \
                    : launch_split_tile<SplitTileSel<6, bm, bn, bk, wm, wn, st>::type>(M, N, K, Ap, Bt, C, ldc,       \
                                                                                        c_is_f64, stream);

@@ -283,11 +283,17 @@ struct SplitTile {
 // swizzled layout puts in its slot.  Rows past M (or N) are clamped to the
 // last row: they only feed entries of C that are not stored.  K is a
 // multiple of 32 (the planes are zero-padded), so no K-tail checks remain.
+//
+// IL (interleaved planes, 2-plane method only): a row of the planes holds, for
+// each 32-element K block, the block of plane 0 and then of plane 1, so one K
+// step of a row is one contiguous 128-byte line (one L2 request) instead of
+// two 64-byte pieces; an LDS row then holds both planes' 8 chunks.
 typedef __attribute__((address_space(3))) void mm_lds_void;
 
-template <int NPROD, int BM_, int BN_, int WM_, int WN_, int STAGES_>
+template <int NPROD, int BM_, int BN_, int WM_, int WN_, int STAGES_, bool IL_ = false>
 struct SplitTileDirect {
     static constexpr bool FUSED = false;
+    static constexpr bool IL = IL_;
     using Terms = SplitTerms<NPROD>;
     static constexpr int NP = Terms::NP;
     static constexpr int BM = BM_, BN = BN_, BK = 32, WM = WM_, WN = WN_;
@@ -311,8 +317,14 @@ struct SplitTileDirect {
     static_assert(STAGES >= 2 && STAGES <= 4, "stages");
     // one load instruction (64 slots = 16 rows) never straddles planes or the A/B boundary
     static_assert(BM % 16 == 0 && BN % 16 == 0, "tile sides in whole 16-row groups");
+    static_assert(!IL || NP == 2, "interleaved planes are for the 2-plane method");
+    // elements of a plane row per K step: one block per plane when interleaved
+    static constexpr int KSTEP = IL ? NP * BK : BK;
 
     static __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 2) & 3); }
+    // Interleaved LDS rows are 128 bytes (8 chunks): the 16 rows one fragment
+    // read touches map to 16 distinct 16-byte bank groups.
+    static __device__ __forceinline__ int swz8(int row, int chunk) { return chunk ^ ((row >> 1) & 7); }
 
     // Source of each load instruction at k = 0 (a K step adds k0): the 64
     // lanes of one instruction fill 16 consecutive rows of one plane, so the
@@ -326,6 +338,26 @@ struct SplitTileDirect {
                                                    const uint16_t *(&base)[LOADS], uint32_t (&voff)[LOADS]) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         const int lane = threadIdx.x & 63;
+        if constexpr (IL) {
+            // an instruction fills 8 whole LDS rows (both planes); the lane
+            // in slot s of row r fetches logical chunk swz8(r, s), which sits
+            // at element 8 * chunk of the row's K block
+#pragma unroll
+            for (int j = 0; j < LOADS; ++j) {
+                const int row0 = (j * NWAVES + wave) * 8;   // wave-uniform
+                const int row = row0 + (lane >> 3);
+                const int c = swz8(row, lane & 7);
+                const bool is_a = row0 < BM;
+                const int64_t first = is_a ? m0 + row0 : n0 + (row0 - BM);
+                const int64_t lim = is_a ? M : N;
+                const int64_t g0 = first < lim ? first : lim - 1;
+                int64_t gr = first + (lane >> 3);
+                gr = gr < lim ? gr : lim - 1;
+                base[j] = (is_a ? Ap : Bt) + g0 * (NP * Kp);
+                voff[j] = (uint32_t)(((gr - g0) * NP * Kp + c * 8) * 2);
+            }
+            return;
+        }
 #pragma unroll
         for (int j = 0; j < LOADS; ++j) {
             const int P0 = (j * NWAVES + wave) * 64;         // first slot of this instruction (wave-uniform)
@@ -362,6 +394,9 @@ struct SplitTileDirect {
     }
 
     static __device__ __forceinline__ bf16x8 frag(const uint16_t *stage, int plane, int row, int q) {
+        if constexpr (IL)
+            return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(stage + row * (NP * 32) +
+                                                                               swz8(row, plane * 4 + q) * 8));
         return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(stage + plane * PLANE_CHUNKS * 8 +
                                                                            row * 32 + swz(row, q) * 8));
     }
@@ -455,7 +490,7 @@ struct SplitTileDirect {
         sources(Ap, pa_stride, Bt, pb_stride, K, m0, n0, M, N, base, voff);
 #pragma unroll
         for (int s = 0; s < STAGES - 1; ++s)
-            if (s < nkt) issue(base, voff, (int64_t)s * BK, smem + s * STAGE_ELEMS);
+            if (s < nkt) issue(base, voff, (int64_t)s * KSTEP, smem + s * STAGE_ELEMS);
         for (int64_t kt = 0; kt < nkt; ++kt) {
             // stage kt has landed once at most the later stages' loads are pending
             const int64_t later = (nkt - 1 - kt) < (STAGES - 2) ? (nkt - 1 - kt) : (STAGES - 2);
@@ -469,7 +504,7 @@ struct SplitTileDirect {
             __builtin_amdgcn_s_barrier();
             compute(smem + (kt % STAGES) * STAGE_ELEMS, lead, corr, [&] {
                 if (kt + STAGES - 1 < nkt)
-                    issue(base, voff, (kt + STAGES - 1) * BK, smem + ((kt + STAGES - 1) % STAGES) * STAGE_ELEMS);
+                    issue(base, voff, (kt + STAGES - 1) * KSTEP, smem + ((kt + STAGES - 1) % STAGES) * STAGE_ELEMS);
             });
         }
         // binary64 recombination of the two accumulator sets
@@ -649,16 +684,18 @@ struct SplitTileFused : SplitTile<NPROD, BM_, BN_, 32, WM_, WN_, 1> {
 // Variant selector: S = 1, 2 register stages (SplitTile); S = 10 + b: direct
 // global-to-LDS ring of b buffers (SplitTileDirect, BK = 32); S = 20: fused
 // split (SplitTileFused, BK = 32, FP32 operands, no plane pass).
-template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, int KIND = (S >= 20 ? 2 : S >= 10 ? 1 : 0)>
+// IL asks the direct tile of the 2-plane method for interleaved planes.
+template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool IL = false,
+          int KIND = (S >= 20 ? 2 : S >= 10 ? 1 : 0)>
 struct SplitTileSel {
     typedef SplitTile<NPROD, BM, BN, BK, WM, WN, S> type;
 };
-template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S>
-struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, 1> {
-    typedef SplitTileDirect<NPROD, BM, BN, WM, WN, S - 10> type;
+template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool IL>
+struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, IL, 1> {
+    typedef SplitTileDirect<NPROD, BM, BN, WM, WN, S - 10, IL && NPROD == 3> type;
 };
-template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S>
-struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, 2> {
+template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool IL>
+struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, IL, 2> {
     static_assert(BK == 32, "the fused tile steps K by 32");
     typedef SplitTileFused<NPROD, BM, BN, WM, WN> type;
 };
