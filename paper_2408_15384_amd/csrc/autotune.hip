@@ -66,9 +66,9 @@ const Candidate kF64Cand[] = {{12, 256, 128, 69.2, false}, {3, 128, 64, 56.5, fa
                               {14, 32, 32, 52.0, false}};
 const Candidate kF32Cand[] = {{12, 256, 128, 141.7, false}, {3, 128, 128, 126.5, false}, {8, 64, 64, 141.0, false},
                               {10, 32, 32, 95.0, false}};
-const Candidate kSplit3Unfused[] = {{14, 256, 128, 366.0, true}, {6, 128, 128, 320.0, true}, {8, 64, 64, 221.6, true}};
+const Candidate kSplit3Unfused[] = {{14, 256, 128, 438.0, true}, {6, 128, 128, 364.0, true}, {8, 64, 64, 319.0, true}};
 const Candidate kSplit6Unfused[] = {{9, 256, 128, 214.0, true}, {6, 128, 128, 190.0, true}, {8, 64, 64, 100.4, true}};
-const Candidate kSplit3Cand[] = {{14, 256, 128, 366.0, true}, {6, 128, 128, 320.0, true},  {8, 64, 64, 221.6, true},
+const Candidate kSplit3Cand[] = {{14, 256, 128, 438.0, true}, {6, 128, 128, 364.0, true},  {8, 64, 64, 319.0, true},
                                  {10, 64, 64, 191.0, false},  {11, 128, 64, 230.6, false}, {12, 128, 128, 204.5, false}};
 const Candidate kSplit6Cand[] = {{9, 256, 128, 214.0, true},  {6, 128, 128, 190.0, true},  {8, 64, 64, 100.4, true},
                                  {10, 64, 64, 126.0, false},  {11, 128, 64, 146.4, false}, {12, 128, 128, 151.6, false}};
