@@ -321,10 +321,17 @@ struct SplitTileDirect {
     // elements of a plane row per K step: one block per plane when interleaved
     static constexpr int KSTEP = IL ? NP * BK : BK;
 
-    static __device__ __forceinline__ int swz(int row, int chunk) { return chunk ^ ((row >> 2) & 3); }
-    // Interleaved LDS rows are 128 bytes (8 chunks): the 16 rows one fragment
-    // read touches map to 16 distinct 16-byte bank groups.
+    // Interleaved LDS rows are 128 bytes (8 chunks), chunk ^ (row/2 mod 8).
+    // Separate planes use 64-byte rows placed so that the 16 rows of a
+    // fragment read hit the same 16-byte bank groups as that layout: within a
+    // 16-row group, 128-byte line l holds rows l and l + 8 (halves), and a
+    // row's 4 chunks sit at chunk ^ (row/2 mod 4).  Both read without bank
+    // conflicts (the plain 64-byte rows with chunk ^ (row/4 mod 4) took twice
+    // the LDS cycles per read).
     static __device__ __forceinline__ int swz8(int row, int chunk) { return chunk ^ ((row >> 1) & 7); }
+    static __device__ __forceinline__ int row_elem(int row, int chunk) {
+        return (row >> 4) * 512 + (row & 7) * 64 + ((row >> 3) & 1) * 32 + ((chunk ^ ((row >> 1) & 3)) * 8);
+    }
 
     // Source of each load instruction at k = 0 (a K step adds k0): the 64
     // lanes of one instruction fill 16 consecutive rows of one plane, so the
@@ -363,13 +370,15 @@ struct SplitTileDirect {
             const int P0 = (j * NWAVES + wave) * 64;         // first slot of this instruction (wave-uniform)
             const int plane = P0 / PLANE_CHUNKS;
             const int row0 = (P0 - plane * PLANE_CHUNKS) >> 2;
-            const int row = row0 + (lane >> 2);              // 16 rows, all of A or all of B (BM % 16 == 0)
-            const int c = swz(row, lane & 3);                // logical chunk stored in this lane's slot
+            // slot i of the 64 (16 rows, all of A or all of B): line i/8 of
+            // the 16-row group, half (i/4) % 2, chunk slot i % 4 (row_elem)
+            const int row = row0 + (lane >> 3) + ((lane >> 2) & 1) * 8;
+            const int c = (lane & 3) ^ ((row >> 1) & 3);     // logical chunk stored in this lane's slot
             const bool is_a = row0 < BM;
             const int64_t first = is_a ? m0 + row0 : n0 + (row0 - BM);
             const int64_t lim = is_a ? M : N;
             const int64_t g0 = first < lim ? first : lim - 1;
-            int64_t gr = first + (lane >> 2);
+            int64_t gr = first + (row - row0);
             gr = gr < lim ? gr : lim - 1;
             base[j] = (is_a ? Ap + plane * pa_stride : Bt + plane * pb_stride) + g0 * Kp;
             voff[j] = (uint32_t)(((gr - g0) * Kp + c * 8) * 2);
@@ -398,7 +407,7 @@ struct SplitTileDirect {
             return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(stage + row * (NP * 32) +
                                                                                swz8(row, plane * 4 + q) * 8));
         return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(stage + plane * PLANE_CHUNKS * 8 +
-                                                                           row * 32 + swz(row, q) * 8));
+                                                                           row_elem(row, q)));
     }
 
     // Plane whose fragments are read just before the products of term t (one
