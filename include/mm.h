@@ -134,12 +134,15 @@ size_t mm_split_workspace_bytes(int64_t M, int64_t N, int64_t K, int32_t nprod);
  *   C         : device; FP32 (c_is_f64 == 0) or binary64 (c_is_f64 != 0), ldc in elements
  *   workspace : device scratch of at least mm_split_workspace_bytes(M,N,K,nprod)
  *               bytes, or NULL to let the library allocate it stream-ordered
- *               when the chosen variant needs it
+ *               when the chosen variant needs it; its layout is internal
+ *               (for nprod = 3 the direct tiles keep the two planes
+ *               interleaved per 32-element K block) and its contents scratch
  * Design error against the exact product: about 4e-6 normwise for nprod = 3 on
  * zero-mean data, below 1e-6 for nprod = 6.  nprod not in {3, 6} is MM_E_INVAL.
  * K above 2^26 - 32 is MM_E_UNSUPPORTED for the split methods (here, in
  * mm_gemm_ex, grouped batches and served requests): the tiles address 16
- * plane rows of K elements with 32-bit byte offsets.
+ * plane rows of K elements (or 8 interleaved rows of 2K) with 32-bit byte
+ * offsets.
  */
 mm_status mm_gemm_split_bf16(int64_t M, int64_t N, int64_t K,
                              const float *A, int64_t lda,
