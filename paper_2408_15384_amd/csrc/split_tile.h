@@ -334,10 +334,11 @@ struct SplitTileDirect {
     }
 
     // Source of each load instruction at k = 0 (a K step adds k0): the 64
-    // lanes of one instruction fill 16 consecutive rows of one plane, so the
-    // instruction reads through a buffer resource based at the first of those
-    // rows (wave-uniform) and each lane adds a 32-bit byte offset below
-    // 16 * Kp * 2, which the entry points keep below 2^31 (K < 2^26).
+    // lanes of one instruction fill 16 consecutive rows of one plane (8 rows
+    // of the interleaved pair), so the instruction reads through a buffer
+    // resource based at the first of those rows (wave-uniform) and each lane
+    // adds a 32-bit byte offset below 16 * Kp * 2, which the entry points keep
+    // below 2^31 (K < 2^26).
 
     static __device__ __forceinline__ void sources(const uint16_t *__restrict__ Ap, int64_t pa_stride,
                                                    const uint16_t *__restrict__ Bt, int64_t pb_stride, int64_t Kp,
