@@ -10,7 +10,8 @@ Contents, each citing what it follows:
 * ``gemm`` / ``gemm_entries`` -- the textbook product of section III (the
   displayed sum over k of A[i][k]*B[k][j]) as the paper's plain triple loop
   (section VI), in binary64, k ascending, no fused multiply-add; written in C
-  (``gemm_ref.c``) and called through ctypes.
+  (``gemm_ref.c``, which walks the loops in i, k, j order without changing
+  any entry's operations) and called through ctypes.
 * ``bf16_round`` / ``split_planes`` / ``split_product`` -- the split-precision
   form: an FP32 matrix is written as a sum of bfloat16 planes (round to
   nearest even at each step), the product is approximated by the sum of a
@@ -22,13 +23,22 @@ Contents, each citing what it follows:
 * ``freivalds`` -- the residual probe r = C.x - A.(B.x) for a given vector x,
   built only from ``gemm`` with N = 1.
 * ``abs_product`` / ``elementwise_bound`` -- |A||B| and the per-entry error
-  bound 4*K*u*(|A||B|)_ij used by the parity tests.
+  bound 4*K*u*(|A||B|)_ij used by the parity tests; ``normwise_rel`` -- the
+  normwise relative error ||C - R||_F / ||R||_F.
+* ``strassen`` / ``strassen_product_bound`` -- one level of the Strassen-
+  Winograd scheme (cited in the literature review) and the per-entry bound
+  between two evaluations of it, carried through its sums.
 
 Pins (tests/test_oracle_pins.py): exact rational brute force, identity and
 zero products, the rank-1 closed form, integer products against exact integer
 arithmetic, K = 1 outer products, transposition symmetry, and a library
 cross-check; for the split form, agreement of ``bf16_round`` with a library
-bfloat16 cast, exact 3-plane reconstruction and the 9-product identity.
+bfloat16 cast, exact 3-plane reconstruction and the 9-product identity;
+hand-worked values of ``normwise_rel``; for the Strassen bound, a worst-case
+second evaluation that stays within it and reaches it, and the exact rational
+evaluation of the scheme.  tests/test_oracle_mutations.py plants slips in
+private copies of the C loop and of the Strassen bound and checks that the
+pins reject each.
 """
 from __future__ import annotations
 
@@ -274,14 +284,41 @@ def strassen(A, B):
 
 def strassen_product_bound(A, B):
     """Per-entry bound on the difference between two evaluations of the
-    scheme whose seven products each lie within 4*k*u*(|X||Y|) of exact (k the
-    inner size), the sums being evaluated identically: the bound is carried
-    through the U-sequence (each U adds the bounds of its terms), with a 1%
-    margin for the roundings of the sums."""
+    scheme that form the S and T sums identically (one binary64 rounding
+    each, in the order above) and whose seven products differ by at most the
+    stated parity bound e_P = 4*k*u*(|X||Y|) (k the inner size K/2).
+
+    The bound is carried through the U-sequence.  For one sum U = X +- Y with
+    inputs that differ by at most e_X and e_Y, rounding to nearest gives
+    fl(v) = v/(1 + d) with |d| <= u, so each side's rounding error is at most
+    u times its own computed |U|; the other side's |U| is at most |U_ref| +
+    e_U.  Hence
+        e_U <= e_X + e_Y + u*|U_ref| + u*(|U_ref| + e_U),
+        e_U <= (e_X + e_Y + 2*u*|U_ref|) / (1 - u),
+    with U_ref this oracle's own computed sums.  The four quadrants take the
+    bound of the U that forms them (C11 = U1, C12 = U5, C21 = U6, C22 = U7)."""
     parts = strassen_parts(A, B)
     k = parts[0][0].shape[1]
-    b = [elementwise_bound(gemm(np.abs(X), np.abs(Y)), k, U_F64) for X, Y in parts]
-    b1, b2, b3, b4, b5, b6, b7 = b
-    u2 = b1 + b6
-    u3 = u2 + b7
-    return 1.01 * np.block([[b1 + b2, u2 + b5 + b3], [u3 + b4, u3 + b5]])
+    e = [elementwise_bound(gemm(np.abs(X), np.abs(Y)), k, U_F64) for X, Y in parts]
+    P = [gemm(X, Y) for X, Y in parts]
+    P1, P2, P3, P4, P5, P6, P7 = P
+    e1, e2, e3, e4, e5, e6, e7 = e
+
+    def carry(ex, ey, U):
+        return (ex + ey + 2.0 * U_F64 * np.abs(U)) / (1.0 - U_F64)
+
+    U1 = P1 + P2
+    U2 = P1 + P6
+    U3 = U2 + P7
+    U4 = U2 + P5
+    U5 = U4 + P3
+    U6 = U3 - P4
+    U7 = U3 + P5
+    f1 = carry(e1, e2, U1)
+    f2 = carry(e1, e6, U2)
+    f3 = carry(f2, e7, U3)
+    f4 = carry(f2, e5, U4)
+    f5 = carry(f4, e3, U5)
+    f6 = carry(f3, e4, U6)
+    f7 = carry(f3, e5, U7)
+    return np.block([[f1, f5], [f6, f7]])

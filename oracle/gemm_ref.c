@@ -11,8 +11,9 @@
  *     C[i][j] = sum over k of A[i][k] * B[k][j].
  * Storage is row-major as in C (section III, storage remark) with explicit
  * leading dimensions; indices are 0-based here where the paper's are 1-based.
- * The loop nest is the paper's plain i, j, k loop (section VI) with OpenMP
- * threads over i (section III-A-1).
+ * The sum is the paper's plain loop (section VI), with OpenMP threads over
+ * rows i (section III-A-1); orc_gemm walks it in i, k, j order, which leaves
+ * every entry's sequence of operations unchanged (see there).
  *
  * Arithmetic is IEEE binary64.  Each entry starts from +0.0 and adds the
  * products in ascending k, each product and each sum rounded once (this file
@@ -31,20 +32,31 @@ int orc_get_threads(void)
     return orc_threads > 0 ? orc_threads : omp_get_max_threads();
 }
 
-/* C (M x N, ldc) = A (M x K, lda) . B (K x N, ldb); all row-major binary64. */
+/* C (M x N, ldc) = A (M x K, lda) . B (K x N, ldb); all row-major binary64.
+ *
+ * The loops run i, k, j rather than the paper's i, j, k: row i of C is the
+ * accumulator and each step k adds A[i][k] * B[k][j] to every entry j of it.
+ * Every entry still receives exactly the operations of the plain loop --
+ * start at +0.0, then for k = 0, 1, ..., K-1 one rounded product and one
+ * rounded sum -- so the bits are those of the i, j, k order; only the walk
+ * over memory changes (B is read along its rows instead of down a column).
+ * C must not overlap A or B. */
 void orc_gemm(int64_t M, int64_t N, int64_t K,
-              const double *A, int64_t lda,
-              const double *B, int64_t ldb,
-              double *C, int64_t ldc)
+              const double *restrict A, int64_t lda,
+              const double *restrict B, int64_t ldb,
+              double *restrict C, int64_t ldc)
 {
     int nt = orc_get_threads();
 #pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
     for (int64_t i = 0; i < M; ++i) {
-        for (int64_t j = 0; j < N; ++j) {
-            double s = 0.0;
-            for (int64_t k = 0; k < K; ++k)
-                s = s + A[i * lda + k] * B[k * ldb + j];
-            C[i * ldc + j] = s;
+        double *restrict c = C + i * ldc;
+        for (int64_t j = 0; j < N; ++j)
+            c[j] = 0.0;
+        for (int64_t k = 0; k < K; ++k) {
+            const double a = A[i * lda + k];
+            const double *restrict b = B + k * ldb;
+            for (int64_t j = 0; j < N; ++j)
+                c[j] = c[j] + a * b[j];
         }
     }
 }

@@ -15,12 +15,12 @@ import oracle
 SRC = os.path.join(os.path.dirname(oracle.__file__), "gemm_ref.c")
 
 MUTANTS = {
-    "dropped_last_term": ("for (int64_t k = 0; k < K; ++k)\n                s = s + A[i * lda + k] * B[k * ldb + j];",
-                          "for (int64_t k = 0; k + 1 < K; ++k)\n                s = s + A[i * lda + k] * B[k * ldb + j];"),
-    "transposed_B": ("s = s + A[i * lda + k] * B[k * ldb + j];", "s = s + A[i * lda + k] * B[j * ldb + k];"),
-    "sign_slip": ("s = s + A[i * lda + k] * B[k * ldb + j];", "s = s - A[i * lda + k] * B[k * ldb + j];"),
-    "wrong_ld": ("s = s + A[i * lda + k] * B[k * ldb + j];", "s = s + A[i * K + k] * B[k * N + j];"),
-    "row_col_swap": ("C[i * ldc + j] = s;", "C[j * ldc + i] = s;"),
+    "dropped_last_term": ("for (int64_t k = 0; k < K; ++k) {", "for (int64_t k = 0; k + 1 < K; ++k) {"),
+    "transposed_B": ("c[j] = c[j] + a * b[j];", "c[j] = c[j] + a * B[j * ldb + k];"),
+    "sign_slip": ("c[j] = c[j] + a * b[j];", "c[j] = c[j] - a * b[j];"),
+    "wrong_ld": ("const double a = A[i * lda + k];\n            const double *restrict b = B + k * ldb;",
+                 "const double a = A[i * K + k];\n            const double *restrict b = B + k * N;"),
+    "row_col_swap": ("c[j]", "C[j * ldc + i]"),
     "fma_contracted": ("-ffp-contract=off", "-ffp-contract=fast"),
 }
 
@@ -95,3 +95,37 @@ def test_mutant_is_caught(tmp_path, name):
         if "__FMA__" not in out:
             pytest.skip("host has no FMA")
     assert not _pins_hold(_build_mutant(tmp_path, name))
+
+
+# Slips in a private copy of the Strassen bound's source: each must let the
+# worst-case second evaluation of the scheme (every product at the edge of its
+# parity bound) fall outside the mutated bound.
+BOUND_MUTANTS = {
+    "dropped_P2_term": ("f1 = carry(e1, e2, U1)", "f1 = carry(e1, 0 * e2, U1)"),
+    "dropped_P3_term": ("f5 = carry(f4, e3, U5)", "f5 = carry(f4, 0 * e3, U5)"),
+    "dropped_P4_term": ("f6 = carry(f3, e4, U6)", "f6 = carry(f3, 0 * e4, U6)"),
+    "skipped_P7_on_C21": ("f6 = carry(f3, e4, U6)", "f6 = carry(f2, e4, U6)"),
+    "no_sum_rounding": ("2.0 * U_F64 * np.abs(U)", "0.0 * np.abs(U)"),
+    "one_side_rounding": ("2.0 * U_F64 * np.abs(U)", "1.0 * U_F64 * np.abs(U)"),
+    "halved_product_bound": ("e = [elementwise_bound(", "e = [0.5 * elementwise_bound("),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BOUND_MUTANTS))
+def test_strassen_bound_mutant_is_caught(name):
+    import inspect
+
+    from paper_2408_15384_amd import inputs as I
+    from test_oracle_pins import STRASSEN_BOUND_SHAPES, _worst_case_second_evaluation
+
+    src = inspect.getsource(oracle.strassen_product_bound)
+    old, new = BOUND_MUTANTS[name]
+    assert old in src, name
+    ns = dict(vars(oracle))
+    exec(src.replace(old, new), ns)
+    mutant = ns["strassen_product_bound"]
+    for (M, N, K) in STRASSEN_BOUND_SHAPES:
+        A, B = I.pair("uniform_f64", M, N, K, seed=K)
+        Q, P = _worst_case_second_evaluation(A, B)
+        assert np.all(np.abs(Q - P) <= oracle.strassen_product_bound(A, B))
+        assert np.any(np.abs(Q - P) > mutant(A, B)), (name, (M, N, K))

@@ -267,14 +267,110 @@ def test_strassen_each_formula_matters():
 
 def test_strassen_float_close_to_product():
     A, B = I.pair("uniform_f64", 96, 80, 128, seed=22)
-    S = oracle.strassen(A, B)
-    R = oracle.gemm(A, B)
     # normwise: a few multiples of the conventional K*u growth
-    assert oracle.normwise_rel(S, R) < 20 * 128 * oracle.U_F64
-    assert np.all(np.abs(S - R) <= oracle.strassen_product_bound(A, B) + oracle.elementwise_bound(
-        oracle.abs_product(A, B), 128, oracle.U_F64) * 4)
+    assert oracle.normwise_rel(oracle.strassen(A, B), oracle.gemm(A, B)) < 20 * 128 * oracle.U_F64
+
+
+def _push(P, e, sign):
+    """The binary64 values farthest from P in direction `sign` that differ
+    from P by at most e, exactly (checked in rational arithmetic)."""
+    Q = (P + sign * e).ravel()
+    Pf, ef = P.ravel(), e.ravel()
+    for t in range(Q.size):
+        while abs(Fraction(float(Q[t])) - Fraction(float(Pf[t]))) > Fraction(float(ef[t])):
+            Q[t] = np.nextafter(Q[t], Pf[t])
+    return Q.reshape(P.shape)
+
+
+def _worst_case_second_evaluation(A, B):
+    """Another evaluation of the scheme whose seven products each sit at the
+    edge of the per-product parity bound 4*k*u*(|X||Y|), with the signs that
+    make every quadrant's deviations add up (P4 enters C21 negated), and whose
+    S, T and U sums are rounded as the oracle rounds them."""
+    parts = oracle.strassen_parts(A, B)
+    k = A.shape[1] // 2
+    P = [oracle.gemm(X, Y) for X, Y in parts]
+    e = [oracle.elementwise_bound(oracle.gemm(np.abs(X), np.abs(Y)), k, oracle.U_F64) for X, Y in parts]
+    signs = [1, 1, 1, -1, 1, 1, 1]
+    Q = [_push(p, ee, sg) for p, ee, sg in zip(P, e, signs)]
+    return oracle.strassen_combine(Q), oracle.strassen_combine(P)
+
+
+# (64, 64, 2) and (66, 98, 34) have inner sizes k = 1 and 17, where the
+# roundings of the U-sums are not small against the product bounds.
+STRASSEN_BOUND_SHAPES = [(64, 64, 2), (66, 98, 34), (40, 56, 128)]
+
+
+@pytest.mark.parametrize("shape", STRASSEN_BOUND_SHAPES)
+def test_strassen_bound_holds_and_is_tight_at_the_worst_case(shape):
+    M, N, K = shape
+    A, B = I.pair("uniform_f64", M, N, K, seed=K)
+    Q, P = _worst_case_second_evaluation(A, B)
+    D = np.abs(Q - P)
+    bound = oracle.strassen_product_bound(A, B)
+    assert np.all(D <= bound)
+    # tight: in every quadrant some entry reaches 80% of the bound (over 99%
+    # once k >= 17); tests/test_oracle_mutations.py shows that a bound missing
+    # any one term falls below this worst case
+    m, n = M // 2, N // 2
+    for qi in (slice(0, m), slice(m, M)):
+        for qj in (slice(0, n), slice(n, N)):
+            assert (D[qi, qj] / bound[qi, qj]).max() >= 0.8
+
+
+@pytest.mark.parametrize("shape", [(2, 2, 2), (4, 6, 4), (6, 4, 8)])
+def test_strassen_bound_against_the_exact_scheme(shape):
+    """Exact rational evaluation of the scheme (products and sums without
+    rounding) is another evaluation whose products lie within gamma_k of the
+    oracle's, inside the parity bound: the oracle's scheme must stay within
+    the carried bound of it."""
+    M, N, K = shape
+    rng = np.random.default_rng(M * 100 + N * 10 + K)
+    A = rng.standard_normal((M, K)) * np.exp2(rng.integers(-6, 6, (M, K)))
+    B = rng.standard_normal((K, N)) * np.exp2(rng.integers(-6, 6, (K, N)))
+    S = oracle.strassen(A, B)
+    bound = oracle.strassen_product_bound(A, B)
+    parts = oracle.strassen_parts(A, B)
+    m, n = M // 2, N // 2
+
+    def mat(X, Y):
+        return [[sum((Fraction(float(X[i, t])) * Fraction(float(Y[t, j])) for t in range(X.shape[1])), Fraction(0))
+                 for j in range(Y.shape[1])] for i in range(X.shape[0])]
+
+    P1, P2, P3, P4, P5, P6, P7 = [mat(X, Y) for X, Y in parts]
+    for i in range(m):
+        for j in range(n):
+            u2 = P1[i][j] + P6[i][j]
+            u3 = u2 + P7[i][j]
+            exact = {(0, 0): P1[i][j] + P2[i][j], (0, 1): u2 + P5[i][j] + P3[i][j],
+                     (1, 0): u3 - P4[i][j], (1, 1): u3 + P5[i][j]}
+            for (qi, qj), v in exact.items():
+                r, c = qi * m + i, qj * n + j
+                assert abs(Fraction(float(S[r, c])) - v) <= Fraction(float(bound[r, c]))
 
 
 def test_strassen_rejects_odd():
     with pytest.raises(ValueError):
         oracle.strassen(np.ones((3, 2)), np.ones((2, 2)))
+
+
+# ------------------------------------------------------------ normwise error
+
+def test_normwise_rel_hand_worked():
+    """||C - R||_F / ||R||_F on hand-worked cases; each catches a different
+    slip (wrong norm, computed value in the denominator, missing square root)."""
+    R = np.ones((2, 2))
+    C = R.copy()
+    C[0, 0] += 0.5
+    # ||C - R||_F = 0.5 and ||R||_F = 2: 0.25 (the max norm would give 0.5,
+    # ||C||_F in the denominator 0.218..., squared norms 0.0625)
+    assert oracle.normwise_rel(C, R) == 0.25
+    C[1, 1] -= 0.5
+    # two entries off by 0.5: sqrt(0.5) / 2 (the max norm would give 0.5 / 1)
+    assert oracle.normwise_rel(C, R) == pytest.approx(0.35355339059327373, rel=1e-15)
+    # the reference, not the computed value, is the scale: |(0, 4)| / |(3, 4)| = 4/5
+    assert oracle.normwise_rel(np.array([[3.0, 0.0]]), np.array([[3.0, 4.0]])) == 0.8
+    # float32 results are widened exactly before the difference is formed
+    R32 = np.array([[1.0, 0.0]])
+    C32 = np.array([[1.0 + 2.0 ** -23, 0.0]], dtype=np.float32)
+    assert oracle.normwise_rel(C32, R32) == 2.0 ** -23
