@@ -151,7 +151,7 @@ def cpu_baseline(A, B, C_gpu, target_s=12.0):
     ratio = float((np.abs(G[:, cols] - R[:, cols]) / np.maximum(4 * K * oracle.U_F64 * absab, 1e-300)).max())
     return {
         "value": flop / dt / 1e12, "unit": "TFLOP/s", "cores": cores, "kind": "oracle",
-        "sample": f"rows 0..{rows - 1} of C for M=N=K={n} binary64 (plain i-j-k loop, OpenMP over rows), "
+        "sample": f"rows 0..{rows - 1} of C for M=N=K={n} binary64 (the plain loop, walked i-k-j, OpenMP over rows), "
                   f"{flop:.3g} FLOP in {dt:.1f} s",
         "gflops": flop / dt / 1e9,
         "cpu_model": _cpu_model(),

@@ -139,6 +139,9 @@ size_t mm_split_workspace_bytes(int64_t M, int64_t N, int64_t K, int32_t nprod);
  *               interleaved per 32-element K block) and its contents scratch
  * Design error against the exact product: about 4e-6 normwise for nprod = 3 on
  * zero-mean data, below 1e-6 for nprod = 6.  nprod not in {3, 6} is MM_E_INVAL.
+ * The binary64 residual check of the result is the separate call
+ * mm_residual_f64 (it needs a caller-chosen probe vector x); enqueued on the
+ * same stream right after this call it runs in stream order behind it.
  * K above 2^26 - 32 is MM_E_UNSUPPORTED for the split methods (here, in
  * mm_gemm_ex, grouped batches and served requests): the tiles address 16
  * plane rows of K elements (or 8 interleaved rows of 2K) with 32-bit byte
@@ -244,8 +247,13 @@ typedef struct mm_grouped_plan mm_grouped_plan;
  * mm_gemm_grouped -- C_i = A_i.B_i for i < count (host array `probs`), all
  * with the same method, each result identical to what the single-problem
  * entry point with the same tile configuration returns.
- *   plan_inout: NULL runs once (descriptors are uploaded and freed after the
- *     launch, stream-ordered).  Otherwise *plan_inout is a plan cache: if it is
+ *   plan_inout: NULL runs once: descriptors (and split workspace) live in a
+ *     stream-ordered allocation freed after the launch, and are uploaded
+ *     through a small ring of library-owned pinned buffers, so the call
+ *     enqueues work and returns without waiting for the stream (it waits at
+ *     most for the upload of the eighth-latest such call on the device).  Not
+ *     for use under stream capture: capture a plan instead.  Otherwise
+ *     *plan_inout is a plan cache: if it is
  *     NULL a plan is built for these shapes (tile map, device descriptor
  *     buffers, split workspace, and a HIP graph of the whole sequence captured
  *     on a stream of the plan's own) and returned; if it is an existing plan
@@ -253,9 +261,10 @@ typedef struct mm_grouped_plan mm_grouped_plan;
  *     graph is replayed on `stream`.  A plan whose shapes differ is
  *     MM_E_INVAL.  A plan holds one set of device descriptors: its launches
  *     are ordered by the stream they are enqueued on, and a caller using one
- *     plan from several streams orders those streams itself.  For split
- *     methods a refresh also waits for `stream` to drain (the split jobs are
- *     copied from host memory).  A plan is owned by the caller and freed with
+ *     plan from several streams orders those streams itself.  A refresh
+ *     copies descriptors and split jobs through the plan's own 4-deep pinned
+ *     ring and does not wait for the stream (at most for the refresh four
+ *     launches back).  A plan is owned by the caller and freed with
  *     mm_grouped_plan_destroy after its last launch finished.
  * count == 0 is a no-op.  Problems with M == 0 or N == 0 are skipped.
  */
@@ -396,14 +405,23 @@ typedef struct mm_serve_stats_t {
  * launches (one per method present) on the free slot's stream, and retires
  * them when the slot's completion event fires.  Requests that arrive while
  * others run are admitted as soon as a slot and budget free up, so their work
- * overlaps on the device.  The server allocates its split workspace inside the
- * budget.
+ * overlaps on the device.  A request is charged its split planes only when its
+ * class's tile variant reads planes (fused variants make none).  Each slot
+ * keeps those planes in a grow-only workspace (it doubles when a batch needs
+ * more; outgrown buffers are kept until mm_serve_destroy, since freeing would
+ * wait for the whole device), which is not charged to the budget: the device
+ * memory a server holds beyond its budget is at most about four times the
+ * planes of the largest batch, per slot.
  */
 mm_status mm_serve_create(const mm_serve_config *cfg, mm_server **out);
 
 /*
  * mm_serve_submit -- enqueue C = A.B (device operands, caller-owned, valid
- * until mm_serve_wait returns for this id).  method: MM_F64, MM_F32,
+ * until mm_serve_wait returns for this id).  A and B must hold their values,
+ * and C must be free to overwrite, when submit is called: the server's slot
+ * streams do not wait for any caller stream, so work that writes A or B, or
+ * still reads or writes C, on another stream must have finished first (e.g.
+ * synchronise that stream before submitting).  method: MM_F64, MM_F32,
  * MM_SPLIT_BF16_3 or MM_SPLIT_BF16_6.  arrival_s is the request's arrival
  * time on the server clock (mm_serve_clock); latency is measured from it, so a
  * client replaying a schedule charges queueing before submission too; pass a

@@ -141,15 +141,29 @@ def _stream(stream) -> int:
 
 
 def _ld(t, name) -> int:
-    if t.dim() != 2:
-        raise ValueError(f"{name} must be 2-D")
+    """Leading dimension of a 2-D GPU tensor used as a row-major matrix."""
     if not t.is_cuda:
         raise ValueError(f"{name} must be a GPU tensor")
+    return row_major_ld(t, name)
+
+
+def row_major_ld(t, name="X") -> int:
+    """Leading dimension (elements between row starts) of a 2-D tensor whose
+    rows are contiguous and do not overlap; ValueError otherwise."""
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be 2-D")
     if t.numel() == 0:
         return max(int(t.shape[1]), 1)
     if t.shape[1] > 1 and t.stride(1) != 1:
         raise ValueError(f"{name} must be row-major (unit column stride)")
-    return max(int(t.stride(0)), int(t.shape[1]), 1)
+    if t.shape[0] > 1 and t.stride(0) < t.shape[1]:
+        # rows overlap (e.g. an expanded or broadcast view): passing the row
+        # length as the leading dimension would make the kernels read or write
+        # past the tensor's storage
+        raise ValueError(f"{name} is not a row-major matrix: row stride {t.stride(0)} < {t.shape[1]} columns")
+    if t.shape[0] == 1:
+        return max(int(t.shape[1]), 1)
+    return int(t.stride(0))
 
 
 def _shapes(A, B):

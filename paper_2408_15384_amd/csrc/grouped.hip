@@ -432,9 +432,11 @@ struct mm_grouped_plan {
     mm::SplitJob *d_jobs = nullptr;
     int *d_counter = nullptr;
     void *ws = nullptr;
-    // pinned staging ring for descriptor refreshes
+    // pinned staging ring for descriptor refreshes: each slot holds the
+    // descriptors, then (at a 256-byte boundary) the split jobs
     static constexpr int RING = 4;
-    mm::GroupedDesc *h_ring = nullptr;
+    char *h_ring = nullptr;
+    size_t ring_stride = 0;
     hipEvent_t ring_ev[RING] = {};
     int ring_pos = 0;
     hipStream_t capture_stream = nullptr;
@@ -484,7 +486,8 @@ static mm_status create_plan(const mm_problem *probs, int32_t count, mm_method m
     if (e == hipSuccess && nd) e = hipMalloc(&p->d_descs, nd * sizeof(GroupedDesc));
     if (e == hipSuccess && nj) e = hipMalloc(&p->d_jobs, nj * sizeof(SplitJob));
     if (e == hipSuccess && schedule == 2) e = hipMalloc(&p->d_counter, sizeof(int));
-    if (e == hipSuccess && nd) e = hipHostMalloc((void **)&p->h_ring, mm_grouped_plan::RING * nd * sizeof(GroupedDesc), 0);
+    p->ring_stride = align256(nd * sizeof(GroupedDesc)) + align256(nj * sizeof(SplitJob));
+    if (e == hipSuccess && nd) e = hipHostMalloc((void **)&p->h_ring, mm_grouped_plan::RING * p->ring_stride, 0);
     for (int i = 0; e == hipSuccess && i < mm_grouped_plan::RING; ++i) e = hipEventCreateWithFlags(&p->ring_ev[i], hipEventDisableTiming);
     if (e == hipSuccess && nd) e = hipMemcpy(p->d_descs, p->layout.descs.data(), nd * sizeof(GroupedDesc), hipMemcpyHostToDevice);
     if (e == hipSuccess && nj) e = hipMemcpy(p->d_jobs, p->layout.jobs.data(), nj * sizeof(SplitJob), hipMemcpyHostToDevice);
@@ -522,17 +525,20 @@ static mm_status run_plan(mm_grouped_plan *p, const mm_problem *probs, hipStream
         // Operand pointers may have changed: rebuild descriptors (the workspace
         // and tile map are unchanged) and refresh them in stream order.
         build_layout(probs, p->order, p->method, p->variant, (char *)p->ws, &p->layout);
+        // The ring slot is reused only once the copies that last read it have
+        // finished (its event), so the call does not wait for the stream.
         const size_t nj = p->layout.jobs.size();
         const int slot = p->ring_pos;
         p->ring_pos = (p->ring_pos + 1) % mm_grouped_plan::RING;
         MM_HIP(hipEventSynchronize(p->ring_ev[slot]));
-        GroupedDesc *h = p->h_ring + slot * nd;
+        char *h = p->h_ring + slot * p->ring_stride;
         std::memcpy(h, p->layout.descs.data(), nd * sizeof(GroupedDesc));
         MM_HIP(hipMemcpyAsync(p->d_descs, h, nd * sizeof(GroupedDesc), hipMemcpyHostToDevice, st));
         if (nj) {
-            // split jobs point at the caller's FP32 operands; they are small, copy synchronously in stream order
-            MM_HIP(hipMemcpyAsync(p->d_jobs, p->layout.jobs.data(), nj * sizeof(SplitJob), hipMemcpyHostToDevice, st));
-            MM_HIP(hipStreamSynchronize(st));
+            // split jobs point at the caller's FP32 operands
+            char *hj = h + align256(nd * sizeof(GroupedDesc));
+            std::memcpy(hj, p->layout.jobs.data(), nj * sizeof(SplitJob));
+            MM_HIP(hipMemcpyAsync(p->d_jobs, hj, nj * sizeof(SplitJob), hipMemcpyHostToDevice, st));
         }
         MM_HIP(hipEventRecord(p->ring_ev[slot], st));
     }
@@ -540,7 +546,64 @@ static mm_status run_plan(mm_grouped_plan *p, const mm_problem *probs, hipStream
     return MM_OK;
 }
 
-// One-shot launch without a plan: descriptors and workspace stream-ordered.
+// Host -> device upload of a one-shot launch's descriptors and split jobs.
+// The bytes are packed into one of a few pinned buffers per device and copied
+// in stream order; an event recorded after the copy guards the buffer, which is
+// reused only once that copy has finished.  The call therefore never waits for
+// the stream's earlier work -- at most for the copy of the call kRing uploads
+// back.  Buffers grow (to the next power of two, 64 KiB at least) and are kept
+// for the life of the process.
+namespace {
+constexpr int kRing = 8;
+struct PinnedSlot {
+    char *host = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+};
+struct PinnedRing {
+    std::mutex mu;
+    PinnedSlot slot[kRing];
+    int pos = 0;
+};
+PinnedRing &pinned_ring(int dev) {
+    static std::mutex mu;
+    static std::map<int, PinnedRing *> rings;   // one per device, never freed
+    std::lock_guard<std::mutex> lock(mu);
+    PinnedRing *&r = rings[dev];
+    if (!r) r = new PinnedRing();
+    return *r;
+}
+}  // namespace
+
+static mm_status upload_staged(char *dst, const void *a, size_t abytes, size_t b_offset, const void *b, size_t bbytes,
+                               hipStream_t st) {
+    int dev = 0;
+    MM_HIP(hipGetDevice(&dev));
+    PinnedRing &r = pinned_ring(dev);
+    std::lock_guard<std::mutex> lock(r.mu);
+    PinnedSlot &s = r.slot[r.pos];
+    r.pos = (r.pos + 1) % kRing;
+    const size_t total = bbytes ? b_offset + bbytes : abytes;
+    if (s.ev) MM_HIP(hipEventSynchronize(s.ev));   // the copy that last read this buffer is done
+    else MM_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
+    if (s.cap < total) {
+        size_t want = (size_t)64 << 10;
+        while (want < total) want *= 2;
+        if (s.host) MM_HIP(hipHostFree(s.host));
+        s.host = nullptr;
+        s.cap = 0;
+        MM_HIP(hipHostMalloc((void **)&s.host, want, 0));
+        s.cap = want;
+    }
+    std::memcpy(s.host, a, abytes);
+    if (bbytes) std::memcpy(s.host + b_offset, b, bbytes);
+    MM_HIP(hipMemcpyAsync(dst, s.host, total, hipMemcpyHostToDevice, st));
+    MM_HIP(hipEventRecord(s.ev, st));
+    return MM_OK;
+}
+
+// One-shot launch without a plan: workspace and descriptors stream-ordered;
+// the call only enqueues work.
 static mm_status run_once(const mm_problem *probs, int32_t count, mm_method method, int variant, int schedule,
                           hipStream_t st) {
     std::vector<int> order = schedule_order(probs, count, schedule);
@@ -558,15 +621,15 @@ static mm_status run_once(const mm_problem *probs, int32_t count, mm_method meth
     GroupedDesc *d_descs = (GroupedDesc *)buf;
     SplitJob *d_jobs = (SplitJob *)(buf + desc_bytes);
     int *d_counter = schedule == 2 ? (int *)(buf + desc_bytes + job_bytes) : nullptr;
-    hipError_t e = hipMemcpyAsync(d_descs, L.descs.data(), nd * sizeof(GroupedDesc), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess && !L.jobs.empty())
-        e = hipMemcpyAsync(d_jobs, L.jobs.data(), L.jobs.size() * sizeof(SplitJob), hipMemcpyHostToDevice, st);
-    // the host vectors must outlive the copies
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e == hipSuccess)
-        e = grouped_enqueue(method, variant, schedule != 3, d_descs, (int)nd, L.total_tiles, d_jobs, (int)L.jobs.size(), L.split_tiles,
-                    d_counter, st);
+    // descriptors then jobs, as laid out in buf
+    mm_status s = upload_staged(buf, L.descs.data(), nd * sizeof(GroupedDesc), desc_bytes, L.jobs.data(),
+                                L.jobs.size() * sizeof(SplitJob), st);
+    hipError_t e = hipSuccess;
+    if (s == MM_OK)
+        e = grouped_enqueue(method, variant, schedule != 3, d_descs, (int)nd, L.total_tiles, d_jobs, (int)L.jobs.size(),
+                            L.split_tiles, d_counter, st);
     hipError_t e2 = hipFreeAsync(buf, st);
+    if (s != MM_OK) return s;
     if (e == hipSuccess) e = e2;
     if (e != hipSuccess) return hip_fail(e, "grouped launch");
     return MM_OK;

@@ -164,3 +164,23 @@ def test_autotune_cache_roundtrip(lib, tmp_path):
     assert api.select_variant("f64", 1000, 1000, 1000) == other
     api.autotune_clear()
     assert api.select_variant("f64", 1000, 1000, 1000) == default
+
+
+def test_binding_rejects_views_that_are_not_row_major_matrices():
+    """Expanded or broadcast views have overlapping rows (row stride below the
+    row length); the binding must refuse them rather than hand the kernels a
+    leading dimension that walks past the tensor's storage."""
+    torch = pytest.importorskip("torch")
+    base = torch.zeros(6, 8, dtype=torch.float64)
+    assert api.row_major_ld(base) == 8
+    assert api.row_major_ld(base[:, :5]) == 8          # column slice: padded rows
+    assert api.row_major_ld(base[2:3, 1:4]) == 3       # one row: its length
+    assert api.row_major_ld(base[:0]) == 8             # empty
+    with pytest.raises(ValueError, match="not a row-major matrix"):
+        api.row_major_ld(torch.zeros(1, 8).expand(6, 8))          # stride(0) == 0
+    with pytest.raises(ValueError, match="not a row-major matrix"):
+        api.row_major_ld(torch.zeros(40).as_strided((6, 8), (4, 1)))   # overlapping rows
+    with pytest.raises(ValueError, match="row-major"):
+        api.row_major_ld(base.t())                      # column-major view
+    with pytest.raises(ValueError, match="GPU tensor"):
+        api._ld(base, "A")

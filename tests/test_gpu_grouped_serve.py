@@ -244,12 +244,14 @@ METHOD_ID = {"f64": 0, "f32": 1, "split3": 2, "split6": 3}
 
 
 def serve_all(mm, reqs, budget, slots, max_batch, one_at_a_time=False, **server_kw):
-    outs = []
+    # the results start as NaN, written on torch's stream; the server's slot
+    # streams do not wait for it, so the fills finish before any submission
+    outs = [torch.full((A.shape[0], B.shape[1]), float("nan"), dtype=DT[method], device="cuda")
+            for method, A, B in reqs]
+    torch.cuda.synchronize()
     with mm.Server(budget_bytes=budget, slots=slots, max_batch=max_batch, **server_kw) as srv:
         ids = []
-        for method, A, B in reqs:
-            C = torch.full((A.shape[0], B.shape[1]), float("nan"), dtype=DT[method], device="cuda")
-            outs.append(C)
+        for (method, A, B), C in zip(reqs, outs):
             rid = srv.submit(A, B, C, METHOD_ID[method])
             if one_at_a_time:
                 st, _ = srv.wait(rid)
