@@ -173,6 +173,26 @@ mm_status mm_residual_f64(int64_t M, int64_t N, int64_t K,
                           void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * mm_residual_f64_noalloc -- mm_residual_f64 for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same arguments, meaning, kernels and result bits
+ * as mm_residual_f64, without the workspace: its temporaries (8*(K + 2M + 512)
+ * bytes) live in a fixed scratch array of the library, 2 MiB per device
+ * (mm_residual_noalloc_max_bytes()), which each device holds from first use
+ * until the process ends.  Shapes needing more return MM_E_INVAL.  The call
+ * allocates nothing and only enqueues kernels on `stream`.  Every call on one
+ * device shares that device's scratch: calls whose work overlaps on the device
+ * (other streams, other threads) race and give wrong results, so the caller
+ * serialises them (e.g. one stream).  Nothing in the scratch needs clearing
+ * between calls.
+ */
+size_t mm_residual_noalloc_max_bytes(void);
+mm_status mm_residual_f64_noalloc(int64_t M, int64_t N, int64_t K,
+                                  const void *A, int64_t lda, const void *B, int64_t ldb,
+                                  const void *C, int64_t ldc, int32_t in_dtype, int32_t c_dtype,
+                                  const double *x, double *out, void *stream);
+
+/*
  * mm_gemm_strassen_f64 -- C = A.B in binary64 by one level of Strassen's
  * scheme in Winograd's form (the sub-cubic method cited in the paper's
  * literature review): A and B are split in 2 x 2 quadrants and C is formed

@@ -78,6 +78,8 @@ EXPORTS = [
     ("mm_gemm_ex", _st, [_st, _st, _st, _i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _p, _sz, _p]),
     ("mm_residual_workspace_bytes", _sz, [_i64, _i64, _i64]),
     ("mm_residual_f64", _st, [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i32, _i32, _p, _p, _p, _sz, _p]),
+    ("mm_residual_noalloc_max_bytes", _sz, []),
+    ("mm_residual_f64_noalloc", _st, [_i64, _i64, _i64, _p, _i64, _p, _i64, _p, _i64, _i32, _i32, _p, _p, _p]),
     ("mm_gemm_grouped", _st, [ctypes.POINTER(Problem), _i32, _st, ctypes.POINTER(_p), _p]),
     ("mm_grouped_plan_destroy", _st, [_p]),
     ("mm_grouped_plan_launch", _st, [_p, _p]),
@@ -281,8 +283,7 @@ def gemm_colmajor_f64(A_cm, B_cm, M: int, N: int, K: int, C_cm=None, stream=None
     return C_cm
 
 
-def residual_f64(A, B, C, x, out=None, workspace=None, stream=None):
-    """Device tensor [||C.x - A.(B.x)||^2, ||A.(B.x)||^2] in binary64 (mm_residual_f64)."""
+def _residual_args(A, B, C, x, out):
     import torch
     M, N, K = _shapes(A, B)
     if tuple(C.shape) != (M, N):
@@ -294,12 +295,25 @@ def residual_f64(A, B, C, x, out=None, workspace=None, stream=None):
         raise ValueError("x must be float64 of length N")
     if out is None:
         out = torch.empty(2, dtype=torch.float64, device=A.device)
+    return (M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"), C.data_ptr(), _ld(C, "C"),
+            code[A.dtype], code[C.dtype], x.data_ptr(), out.data_ptr()), out
+
+
+def residual_f64(A, B, C, x, out=None, workspace=None, stream=None):
+    """Device tensor [||C.x - A.(B.x)||^2, ||A.(B.x)||^2] in binary64 (mm_residual_f64)."""
+    args, out = _residual_args(A, B, C, x, out)
     ws_ptr, ws_bytes = 0, 0
     if workspace is not None:
         ws_ptr, ws_bytes = workspace.data_ptr(), workspace.numel() * workspace.element_size()
-    check(lib().mm_residual_f64(M, N, K, A.data_ptr(), _ld(A, "A"), B.data_ptr(), _ld(B, "B"), C.data_ptr(),
-                                _ld(C, "C"), code[A.dtype], code[C.dtype], x.data_ptr(), out.data_ptr(),
-                                ws_ptr or None, ws_bytes, _stream(stream)))
+    check(lib().mm_residual_f64(*args, ws_ptr or None, ws_bytes, _stream(stream)))
+    return out
+
+
+def residual_f64_noalloc(A, B, C, x, out=None, stream=None):
+    """mm_residual_f64_noalloc: the same probe with the library's fixed scratch
+    (no device allocation by the library; `out` is allocated here if None)."""
+    args, out = _residual_args(A, B, C, x, out)
+    check(lib().mm_residual_f64_noalloc(*args, _stream(stream)))
     return out
 
 

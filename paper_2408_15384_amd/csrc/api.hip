@@ -155,7 +155,11 @@ const char *mm_last_error(void) { return g_last_error.c_str(); }
 mm_status mm_init(int device) {
     MM_GUARD_BEGIN
     MM_HIP(hipSetDevice(device));
-    return check_arch();
+    mm_status s = check_arch();
+    if (s != MM_OK) return s;
+    // device address of the no-allocation entry point's scratch
+    MM_HIP(residual_scratch_init());
+    return MM_OK;
     MM_GUARD_END
 }
 
@@ -385,10 +389,10 @@ size_t mm_residual_workspace_bytes(int64_t M, int64_t N, int64_t K) {
     return residual_workspace_bytes(M, N, K);
 }
 
-mm_status mm_residual_f64(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B, int64_t ldb,
-                          const void *C, int64_t ldc, int32_t in_dtype, int32_t c_dtype, const double *x, double *out,
-                          void *workspace, size_t workspace_bytes, void *stream) {
-    MM_GUARD_BEGIN
+// Argument checks of the residual probe (both entry points).
+static mm_status check_residual_args(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
+                                     int64_t ldb, const void *C, int64_t ldc, int32_t in_dtype, int32_t c_dtype,
+                                     const double *x, const double *out) {
     if ((in_dtype != 0 && in_dtype != 1) || (c_dtype != 0 && c_dtype != 1))
         return fail(MM_E_INVAL, "dtype must be 0 (binary64) or 1 (FP32)");
     if (M < 0 || N < 0 || K < 0) return fail(MM_E_INVAL, "negative dimension");
@@ -400,7 +404,14 @@ mm_status mm_residual_f64(int64_t M, int64_t N, int64_t K, const void *A, int64_
     if (!out) return fail(MM_E_INVAL, "out is NULL");
     if ((M > 0 && K > 0 && !A) || (K > 0 && N > 0 && !B) || (M > 0 && N > 0 && !C) || (N > 0 && !x))
         return fail(MM_E_INVAL, "NULL operand");
-    mm_status s = check_arch();
+    return check_arch();
+}
+
+mm_status mm_residual_f64(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B, int64_t ldb,
+                          const void *C, int64_t ldc, int32_t in_dtype, int32_t c_dtype, const double *x, double *out,
+                          void *workspace, size_t workspace_bytes, void *stream) {
+    MM_GUARD_BEGIN
+    mm_status s = check_residual_args(M, N, K, A, lda, B, ldb, C, ldc, in_dtype, c_dtype, x, out);
     if (s != MM_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     const size_t need = residual_workspace_bytes(M, N, K);
@@ -418,6 +429,24 @@ mm_status mm_residual_f64(int64_t M, int64_t N, int64_t K, const void *A, int64_
         if (e == hipSuccess) e = e2;
     }
     if (e != hipSuccess) return hip_fail(e, "residual launch");
+    return MM_OK;
+    MM_GUARD_END
+}
+
+size_t mm_residual_noalloc_max_bytes(void) { return kResidualScratchDoubles * sizeof(double); }
+
+mm_status mm_residual_f64_noalloc(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
+                                  int64_t ldb, const void *C, int64_t ldc, int32_t in_dtype, int32_t c_dtype,
+                                  const double *x, double *out, void *stream) {
+    MM_GUARD_BEGIN
+    mm_status s = check_residual_args(M, N, K, A, lda, B, ldb, C, ldc, in_dtype, c_dtype, x, out);
+    if (s != MM_OK) return s;
+    if (residual_workspace_bytes(M, N, K) > kResidualScratchDoubles * sizeof(double))
+        return fail(MM_E_INVAL, "residual scratch needs 8*(K + 2M + 512) bytes; the fixed scratch holds 2 MiB "
+                                "(use mm_residual_f64 with a workspace for larger shapes)");
+    void *ws = nullptr;
+    MM_HIP(residual_scratch(&ws));
+    MM_HIP(launch_residual(M, N, K, A, lda, B, ldb, C, ldc, in_dtype, c_dtype, x, out, ws, (hipStream_t)stream));
     return MM_OK;
     MM_GUARD_END
 }

@@ -92,6 +92,13 @@ size_t residual_workspace_bytes(int64_t M, int64_t N, int64_t K);
 hipError_t launch_residual(int64_t M, int64_t N, int64_t K, const void *A, int64_t lda, const void *B,
                            int64_t ldb, const void *C, int64_t ldc, int in_dtype, int c_dtype, const double *x,
                            double *out, void *ws, hipStream_t stream);
+// Fixed per-device scratch of the no-allocation residual entry point:
+// kResidualScratchDoubles binary64 values (2 MiB).  residual_scratch_init looks
+// up the current device's address of the array once; residual_scratch returns
+// it (looking it up on first use).
+constexpr size_t kResidualScratchDoubles = (size_t)1 << 18;
+hipError_t residual_scratch_init();
+hipError_t residual_scratch(void **ptr);
 
 // Y (cols x rows, leading dim ldy) = X^T for X rows x cols (leading dim ldx).
 hipError_t launch_transpose(const void *X, int64_t ldx, int64_t rows, int64_t cols, void *Y, int64_t ldy,

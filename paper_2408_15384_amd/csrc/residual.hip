@@ -1,6 +1,9 @@
 // Residual probe of a computed product (Freivalds): for a probe vector x,
 // y = B.x, z = A.y, w = C.x, r = w - z, all in binary64, reduced to
 // ||r||^2 and ||z||^2 in a fixed order (deterministic, no atomics).
+#include <mutex>
+#include <vector>
+
 #include "mm_internal.h"
 
 namespace mm {
@@ -114,6 +117,46 @@ hipError_t launch_residual(int64_t M, int64_t N, int64_t K, const void *A, int64
     hipLaunchKernelGGL(residual_partials_kernel, dim3(kPartials), dim3(256), 0, st, w, z, M, partials);
     hipLaunchKernelGGL(residual_final_kernel, dim3(1), dim3(256), 0, st, partials, out);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------ no-allocation form
+// Fixed device scratch for mm_residual_f64_noalloc: y, z, w and the partial
+// sums live here instead of in a caller workspace or a stream-ordered
+// allocation.  Each device holds its own copy of the array (at its own
+// address) for the life of the process.  The host must never use the array's
+// name as an address: its device address is looked up once per device
+// (hipGetSymbolAddress, with that device current) and kept.
+static __device__ __align__(256) double scratch[kResidualScratchDoubles];
+
+namespace {
+std::mutex g_scratch_mu;
+std::vector<void *> g_scratch_ptr;   // index: device ordinal; nullptr until looked up
+}  // namespace
+
+hipError_t residual_scratch_init() {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize(dev + 1, nullptr);
+    if (g_scratch_ptr[dev]) return hipSuccess;
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[dev] = p;
+    return hipSuccess;
+}
+
+hipError_t residual_scratch(void **ptr) {
+    hipError_t e = residual_scratch_init();
+    if (e != hipSuccess) return e;
+    int dev = 0;
+    e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace mm
