@@ -20,6 +20,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "mm_internal.h"
@@ -76,6 +77,7 @@ __device__ __forceinline__ int64_t uniform(int64_t v) {
 // chunk c goes to XCD c % 8, so every XCD still takes heavy and light work in
 // the order of the tile map.  A bijection on [0, round_up(tiles, 8 kChunk)).
 constexpr int kChunk = 8;
+constexpr int kCounters = 8;   // work counters of schedule 2 (the streamed form uses one per XCD)
 __device__ __forceinline__ int64_t chunked_tile(int64_t bid) {
     const int64_t xcd = bid % 8, local = bid / 8;
     return ((local / kChunk) * 8 + xcd) * kChunk + local % kChunk;
@@ -150,7 +152,7 @@ __device__ __forceinline__ void grouped_split_tile(const GroupedDesc *__restrict
 // share a CU; otherwise one.
 template <typename TG, typename T, bool PERSISTENT>
 __global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 && TG::LDS_ELEMS * sizeof(T) <= 76 * 1024 ? 2 : 1)) void grouped_gemm_kernel(
-    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter) {
+    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter, const TileRef *) {
     __shared__ __attribute__((aligned(16))) T smem[TG::LDS_ELEMS];
     if constexpr (PERSISTENT) {
         __shared__ int32_t s_begin[kOwnerCap];
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 && TG::LDS_ELEMS * sizeof(
 
 template <typename ST, bool PERSISTENT>
 __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void grouped_split_gemm_kernel(
-    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter) {
+    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter, const TileRef *) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
     if constexpr (PERSISTENT) {
         __shared__ int32_t s_begin[kOwnerCap];
@@ -190,6 +192,86 @@ __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void grouped_spl
             grouped_split_tile<ST>(descs, uniform(find_owner(descs, (const int32_t *)nullptr, false, count, t)), t,
                                    smem);
     }
+}
+
+// Streamed persistent form of the fused ring tiles: each workgroup runs its
+// sequence of tiles as one stream of K steps, loading the next tile's first
+// steps while the current tile is multiplied (SplitTileFusedRing::run_stream).
+// Without a counter a workgroup takes tiles blockIdx.x + i * gridDim.x;
+// with one (schedule 2) its first tile is blockIdx.x and each
+// further tile is gridDim.x + a ticket of the work counter, drawn by thread 0
+// as soon as the previous tile is opened for loading and passed to the other
+// waves through a small LDS ring (a barrier precedes each read).  Every
+// problem of the batch satisfies the tile's offset limits (checked on the
+// host).
+struct StaticSeq {
+    int64_t first, stride;
+    __device__ __forceinline__ int64_t tile(int i) const { return first + (int64_t)i * stride; }
+    __device__ __forceinline__ void draw(int) {}
+};
+
+// Tickets per XCD: the workgroups of XCD x (blockIdx.x % 8, since workgroups
+// are dispatched to the XCDs round-robin) walk that XCD's share of the tile
+// map -- chunks of kChunk consecutive tiles, chunk c on XCD c % 8, as the
+// one-workgroup-per-tile form places them -- drawing positions from the XCD's
+// own counter, so tiles that share a problem's panels share an L2.  The grid
+// is a multiple of 8.
+struct TicketSeq {
+    int *counter;     // 8 counters, one per XCD
+    int64_t *ring;    // LDS, 8 entries: tile of sequence position i at i % 8
+    __device__ __forceinline__ static int64_t chunked(int64_t xcd, int64_t local) {
+        return ((local / kChunk) * 8 + xcd) * kChunk + local % kChunk;
+    }
+    __device__ __forceinline__ int64_t tile(int i) const {
+        if (i == 0) return chunked(blockIdx.x % 8, blockIdx.x / 8);
+        __syncthreads();   // thread 0's write of position i is visible
+        return uniform(ring[i & 7]);
+    }
+    __device__ __forceinline__ void draw(int i) {
+        if (threadIdx.x == 0) {
+            const int x = blockIdx.x % 8;
+            ring[(i + 1) & 7] = chunked(x, (int64_t)(gridDim.x / 8) + atomicAdd(counter + x, 1));
+        }
+    }
+};
+
+// Waves per SIMD the streamed kernel is compiled for: as many 4-wave
+// workgroups as the CU's LDS holds (the one-workgroup-per-tile kernel reaches
+// that occupancy by itself; the stream's extra state must not lower it).
+template <typename ST>
+constexpr int stream_waves() {
+    constexpr int lds = ST::LDS_ELEMS * 2 + 64;
+    constexpr int wgs = (160 * 1024) / lds;
+    constexpr int w = wgs * ST::NWAVES / 4;
+    return w < 1 ? 1 : (w > 4 ? 4 : w);
+}
+
+template <typename ST>
+__global__ __launch_bounds__(ST::NT, stream_waves<ST>()) void grouped_split_stream_kernel(const GroupedDesc *__restrict__ descs,
+                                                                          int count, int64_t total_tiles,
+                                                                          int *counter,
+                                                                          const TileRef *__restrict__ tiles) {
+    __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
+    __shared__ int64_t s_ring[8];
+    (void)count;
+    auto decode = [&](int64_t t, typename ST::Geo &g) {
+        const TileRef ref = tiles[t];
+        const GroupedDesc &d = descs[uniform(ref.own)];
+        const int64_t tm = uniform(ref.tm), tn = uniform(ref.tn);
+        g.A = (const float *)d.A;
+        g.B = (const float *)d.B;
+        g.C = d.C;
+        g.lda = d.lda;
+        g.ldb = d.ldb;
+        g.ldc = d.ldc;
+        g.M = d.M;
+        g.N = d.N;
+        g.K = d.K;
+        g.tm = tm;
+        g.tn = tn;
+    };
+    if (counter) ST::run_stream(total_tiles, 0, TicketSeq{counter, s_ring}, decode, smem);
+    else ST::run_stream(total_tiles, 0, StaticSeq{blockIdx.x, gridDim.x}, decode, smem);
 }
 
 __global__ __launch_bounds__(256) void grouped_split_kernel(const SplitJob *__restrict__ jobs, int njobs,
@@ -244,8 +326,9 @@ __global__ __launch_bounds__(256) void grouped_split_kernel(const SplitJob *__re
     }
 }
 
+// Clears the work counters (one per XCD) with a kernel, not a memset node.
 __global__ void reset_counter_kernel(int *counter) {
-    if (threadIdx.x == 0) *counter = 0;
+    if (threadIdx.x < kCounters) counter[threadIdx.x] = 0;
 }
 
 // ------------------------------------------------------------------ variants
@@ -255,18 +338,42 @@ typedef const void *KernelPtr;
 struct KernelInfo {
     KernelPtr fn = nullptr;
     int nt = 0, bm = 0, bn = 0;
+    bool stream = false;   // a streamed persistent form exists (ring-fused split tiles)
 };
 
-static KernelInfo kernel_for(mm_method method, int variant, bool persistent = true) {
+// Ring-fused split tiles (the only ones with a streamed persistent form).
+template <typename T, typename = void> struct has_ring : std::false_type {};
+template <typename T> struct has_ring<T, std::void_t<decltype(T::RS)>> : std::true_type {};
+
+template <typename TG, typename T>
+static KernelPtr dense_kernel(int form) {
+    return form == kFormTile ? (KernelPtr)&grouped_gemm_kernel<TG, T, false>
+                             : (KernelPtr)&grouped_gemm_kernel<TG, T, true>;
+}
+
+template <typename ST>
+static KernelPtr split_kernel(int form) {
+    if (form == kFormStream) {
+        if constexpr (has_ring<ST>::value) return (KernelPtr)&grouped_split_stream_kernel<ST>;
+        return nullptr;
+    }
+    return form == kFormTile ? (KernelPtr)&grouped_split_gemm_kernel<ST, false>
+                             : (KernelPtr)&grouped_split_gemm_kernel<ST, true>;
+}
+
+template <typename ST>
+static constexpr bool split_has_stream() { return has_ring<ST>::value; }
+
+static KernelInfo kernel_for(mm_method method, int variant, int form = kFormPersistent) {
     KernelInfo k;
 #define MM_GK_F64(id, bm_, bn_, bk, wm, wn, st) \
-    case id: k.fn = persistent ? (KernelPtr)&grouped_gemm_kernel<TileSel<double, bm_, bn_, bk, wm, wn, st>::type, double, true> : (KernelPtr)&grouped_gemm_kernel<TileSel<double, bm_, bn_, bk, wm, wn, st>::type, double, false>; k.nt = TileSel<double, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
+    case id: { typedef TileSel<double, bm_, bn_, bk, wm, wn, st>::type TG; k.fn = form == kFormStream ? nullptr : dense_kernel<TG, double>(form); k.nt = TG::NT; k.bm = bm_; k.bn = bn_; break; }
 #define MM_GK_F32(id, bm_, bn_, bk, wm, wn, st) \
-    case id: k.fn = persistent ? (KernelPtr)&grouped_gemm_kernel<TileSel<float, bm_, bn_, bk, wm, wn, st>::type, float, true> : (KernelPtr)&grouped_gemm_kernel<TileSel<float, bm_, bn_, bk, wm, wn, st>::type, float, false>; k.nt = TileSel<float, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
+    case id: { typedef TileSel<float, bm_, bn_, bk, wm, wn, st>::type TG; k.fn = form == kFormStream ? nullptr : dense_kernel<TG, float>(form); k.nt = TG::NT; k.bm = bm_; k.bn = bn_; break; }
 #define MM_GK_S3(id, bm_, bn_, bk, wm, wn, st) \
-    case id: k.fn = persistent ? (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type, true> : (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type, false>; k.nt = SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
+    case id: { typedef SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type ST; k.fn = split_kernel<ST>(form); k.nt = ST::NT; k.bm = bm_; k.bn = bn_; k.stream = split_has_stream<ST>(); break; }
 #define MM_GK_S6(id, bm_, bn_, bk, wm, wn, st) \
-    case id: k.fn = persistent ? (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type, true> : (KernelPtr)&grouped_split_gemm_kernel<SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type, false>; k.nt = SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type::NT; k.bm = bm_; k.bn = bn_; break;
+    case id: { typedef SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type ST; k.fn = split_kernel<ST>(form); k.nt = ST::NT; k.bm = bm_; k.bn = bn_; k.stream = split_has_stream<ST>(); break; }
     switch (method) {
         case MM_F64: switch (variant) { MM_F64_VARIANTS(MM_GK_F64) default: break; } break;
         case MM_F32: switch (variant) { MM_F32_VARIANTS(MM_GK_F32) default: break; } break;
@@ -276,17 +383,23 @@ static KernelInfo kernel_for(mm_method method, int variant, bool persistent = tr
     return k;
 }
 
+int grouped_form(mm_method method, int variant, int schedule, const Layout &L) {
+    if (schedule == 3) return kFormTile;
+    if (L.ring_ok && kernel_for(method, variant, kFormTile).stream) return kFormStream;
+    return kFormPersistent;
+}
+
 int grouped_tile_bm(mm_method method, int variant) { return kernel_for(method, variant).bm; }
 int grouped_tile_bn(mm_method method, int variant) { return kernel_for(method, variant).bn; }
 
 // Workgroups of `fn` resident on the whole chip at once.
-static int persistent_grid(mm_method method, int variant, KernelPtr fn, int nt) {
+static int persistent_grid(KernelPtr fn, int nt) {
     static std::mutex mu;
-    static std::map<std::pair<int, int>, int> cache;
+    static std::map<std::pair<int, KernelPtr>, int> cache;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     std::lock_guard<std::mutex> lock(mu);
-    auto key = std::make_pair(dev * 64 + (int)method, variant);
+    auto key = std::make_pair(dev, fn);
     auto it = cache.find(key);
     if (it != cache.end()) return it->second;
     int per_cu = 1;
@@ -296,6 +409,19 @@ static int persistent_grid(mm_method method, int variant, KernelPtr fn, int nt) 
     const int g = per_cu * cus;
     cache[key] = g;
     return g;
+}
+
+// Workgroups of a grouped launch: one per tile (rounded up so that runs of
+// kChunk tiles go to one XCD), or the persistent grid capped by the tile count
+// (the streamed form keeps it a multiple of 8: its tickets are per XCD).
+static int64_t launch_grid(int form, const KernelInfo &k, int64_t total_tiles) {
+    if (form == kFormTile) return chunked_grid(total_tiles);
+    int64_t g = persistent_grid(k.fn, k.nt);
+    if (form == kFormStream) {
+        const int64_t cap = (total_tiles + 7) / 8 * 8;
+        return g < cap ? g : cap;
+    }
+    return g < total_tiles ? g : total_tiles;
 }
 
 // ------------------------------------------------------------------ host layout
@@ -316,6 +442,7 @@ void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_met
     L->jobs.clear();
     L->total_tiles = 0;
     L->split_tiles = 0;
+    L->ring_ok = true;
     size_t off = 0;
     for (int idx : order) {
         const mm_problem &p = probs[idx];
@@ -335,6 +462,9 @@ void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_met
         d.tiles_m = (int32_t)cdiv(p.M, bm);
         d.tile_begin = L->total_tiles;
         L->total_tiles += cdiv(p.M, bm) * d.tiles_n;
+        // per-lane byte offsets of the ring-fused tiles (BK = 32) fit 31 bits
+        if (((int64_t)(bm - 1) * p.lda + 32) * 4 >= 0x7fff0000LL || ((int64_t)31 * p.ldb + bn) * 4 >= 0x7fff0000LL)
+            L->ring_ok = false;
         if (split) {
             const int64_t Kp = split_padded_k(p.K);
             const size_t abytes = align256((size_t)np * p.M * Kp * 2);
@@ -363,6 +493,27 @@ void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_met
     L->ws_bytes = off;
 }
 
+// Tile coordinates in the order the device's local_tile gives them:
+// column-major within groups of two tile rows.
+void build_tile_table(const Layout &L, std::vector<TileRef> *out) {
+    out->resize((size_t)L.total_tiles);
+    for (size_t i = 0; i < L.descs.size(); ++i) {
+        const GroupedDesc &d = L.descs[i];
+        const int64_t n = (int64_t)d.tiles_m * d.tiles_n;
+        for (int64_t local = 0; local < n; ++local) {
+            const int64_t per_group = 2 * (int64_t)d.tiles_n;
+            const int64_t first_m = (local / per_group) * 2;
+            const int64_t gsize = d.tiles_m - first_m < 2 ? d.tiles_m - first_m : 2;
+            const int64_t in = local % per_group;
+            TileRef &r = (*out)[(size_t)(d.tile_begin + local)];
+            r.own = (int32_t)i;
+            r.tm = (int32_t)(first_m + in % gsize);
+            r.tn = (int32_t)(in / gsize);
+            r.pad = 0;
+        }
+    }
+}
+
 // Launch order of the problems.  0: as given; 1, 2 and 3: largest K*M*N first
 // (heaviest tiles start first).  How tiles reach workgroups: 0 and 1 a
 // persistent grid by fixed stride, 2 a persistent grid pulling from a work
@@ -383,11 +534,12 @@ std::vector<int> schedule_order(const mm_problem *probs, int count, int schedule
 // Enqueue the whole grouped sequence for descriptors already on the device.
 // d_counter (schedule 2 only) is the work counter; persistent == false runs
 // one workgroup per tile (schedule 3).
-hipError_t grouped_enqueue(mm_method method, int variant, bool persistent, const GroupedDesc *d_descs, int ndesc,
+hipError_t grouped_enqueue(mm_method method, int variant, int form, const GroupedDesc *d_descs, int ndesc,
                           int64_t total_tiles, const SplitJob *d_jobs, int njobs, int64_t split_tiles, int *d_counter,
-                          hipStream_t st) {
+                          const TileRef *d_tiles, hipStream_t st) {
     if (ndesc == 0) return hipSuccess;
-    const KernelInfo k = kernel_for(method, variant, persistent);
+    const bool persistent = form != kFormTile;
+    const KernelInfo k = kernel_for(method, variant, form);
     if (!k.fn) return hipErrorInvalidValue;
     if (!persistent && chunked_grid(total_tiles) > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     if (njobs > 0 && split_tiles > 0) {
@@ -396,9 +548,9 @@ hipError_t grouped_enqueue(mm_method method, int variant, bool persistent, const
     }
     if (!persistent) d_counter = nullptr;
     if (d_counter) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, d_counter);
-    int64_t grid = persistent ? persistent_grid(method, variant, k.fn, k.nt) : chunked_grid(total_tiles);
-    if (persistent && grid > total_tiles) grid = total_tiles;
-    void *args[] = {(void *)&d_descs, (void *)&ndesc, (void *)&total_tiles, (void *)&d_counter};
+    const int64_t grid = launch_grid(form, k, total_tiles);
+    if (form == kFormStream && !d_tiles) return hipErrorInvalidValue;
+    void *args[] = {(void *)&d_descs, (void *)&ndesc, (void *)&total_tiles, (void *)&d_counter, (void *)&d_tiles};
     return hipLaunchKernel(k.fn, dim3((unsigned)grid), dim3(k.nt), args, 0, st);
 }
 
@@ -431,6 +583,7 @@ struct mm_grouped_plan {
     mm::GroupedDesc *d_descs = nullptr;
     mm::SplitJob *d_jobs = nullptr;
     int *d_counter = nullptr;
+    mm::TileRef *d_tiles = nullptr;   // streamed form only
     void *ws = nullptr;
     // pinned staging ring for descriptor refreshes: each slot holds the
     // descriptors, then (at a 256-byte boundary) the split jobs
@@ -462,6 +615,7 @@ static void destroy_plan(mm_grouped_plan *p) {
     if (p->d_descs) (void)hipFree(p->d_descs);
     if (p->d_jobs) (void)hipFree(p->d_jobs);
     if (p->d_counter) (void)hipFree(p->d_counter);
+    if (p->d_tiles) (void)hipFree(p->d_tiles);
     if (p->ws) (void)hipFree(p->ws);
     delete p;
 }
@@ -485,7 +639,16 @@ static mm_status create_plan(const mm_problem *probs, int32_t count, mm_method m
     const size_t nd = p->layout.descs.size(), nj = p->layout.jobs.size();
     if (e == hipSuccess && nd) e = hipMalloc(&p->d_descs, nd * sizeof(GroupedDesc));
     if (e == hipSuccess && nj) e = hipMalloc(&p->d_jobs, nj * sizeof(SplitJob));
-    if (e == hipSuccess && schedule == 2) e = hipMalloc(&p->d_counter, sizeof(int));
+    if (e == hipSuccess && schedule == 2) e = hipMalloc(&p->d_counter, kCounters * sizeof(int));
+    const int form = grouped_form(method, variant, schedule, p->layout);
+    if (e == hipSuccess && form == kFormStream && p->layout.total_tiles > 0) {
+        // the tile table depends on the shapes only: uploaded once
+        std::vector<TileRef> table;
+        build_tile_table(p->layout, &table);
+        e = hipMalloc(&p->d_tiles, table.size() * sizeof(TileRef));
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d_tiles, table.data(), table.size() * sizeof(TileRef), hipMemcpyHostToDevice);
+    }
     p->ring_stride = align256(nd * sizeof(GroupedDesc)) + align256(nj * sizeof(SplitJob));
     if (e == hipSuccess && nd) e = hipHostMalloc((void **)&p->h_ring, mm_grouped_plan::RING * p->ring_stride, 0);
     for (int i = 0; e == hipSuccess && i < mm_grouped_plan::RING; ++i) e = hipEventCreateWithFlags(&p->ring_ev[i], hipEventDisableTiming);
@@ -495,8 +658,8 @@ static mm_status create_plan(const mm_problem *probs, int32_t count, mm_method m
     if (e == hipSuccess && nd) {
         e = hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            hipError_t le = grouped_enqueue(method, variant, schedule != 3, p->d_descs, (int)nd, p->layout.total_tiles, p->d_jobs, (int)nj,
-                                    p->layout.split_tiles, p->d_counter, p->capture_stream);
+            hipError_t le = grouped_enqueue(method, variant, form, p->d_descs, (int)nd, p->layout.total_tiles, p->d_jobs, (int)nj,
+                                    p->layout.split_tiles, p->d_counter, p->d_tiles, p->capture_stream);
             hipError_t ce = hipStreamEndCapture(p->capture_stream, &p->graph);
             e = le != hipSuccess ? le : ce;
         }
@@ -575,15 +738,25 @@ PinnedRing &pinned_ring(int dev) {
 }
 }  // namespace
 
-static mm_status upload_staged(char *dst, const void *a, size_t abytes, size_t b_offset, const void *b, size_t bbytes,
-                               hipStream_t st) {
+// One piece of an upload: `bytes` from host `src` to byte `offset` of the
+// destination.
+struct Piece {
+    size_t offset;
+    const void *src;
+    size_t bytes;
+};
+
+static mm_status upload_staged(char *dst, const Piece *pieces, int npieces, hipStream_t st) {
     int dev = 0;
     MM_HIP(hipGetDevice(&dev));
+    size_t total = 0;
+    for (int i = 0; i < npieces; ++i)
+        if (pieces[i].bytes) total = std::max(total, pieces[i].offset + pieces[i].bytes);
+    if (total == 0) return MM_OK;
     PinnedRing &r = pinned_ring(dev);
     std::lock_guard<std::mutex> lock(r.mu);
     PinnedSlot &s = r.slot[r.pos];
     r.pos = (r.pos + 1) % kRing;
-    const size_t total = bbytes ? b_offset + bbytes : abytes;
     if (s.ev) MM_HIP(hipEventSynchronize(s.ev));   // the copy that last read this buffer is done
     else MM_HIP(hipEventCreateWithFlags(&s.ev, hipEventDisableTiming));
     if (s.cap < total) {
@@ -595,8 +768,8 @@ static mm_status upload_staged(char *dst, const void *a, size_t abytes, size_t b
         MM_HIP(hipHostMalloc((void **)&s.host, want, 0));
         s.cap = want;
     }
-    std::memcpy(s.host, a, abytes);
-    if (bbytes) std::memcpy(s.host + b_offset, b, bbytes);
+    for (int i = 0; i < npieces; ++i)
+        if (pieces[i].bytes) std::memcpy(s.host + pieces[i].offset, pieces[i].src, pieces[i].bytes);
     MM_HIP(hipMemcpyAsync(dst, s.host, total, hipMemcpyHostToDevice, st));
     MM_HIP(hipEventRecord(s.ev, st));
     return MM_OK;
@@ -611,23 +784,31 @@ static mm_status run_once(const mm_problem *probs, int32_t count, mm_method meth
     build_layout(probs, order, method, variant, nullptr, &L);
     const size_t nd = L.descs.size();
     if (nd == 0) return MM_OK;
-    char *buf = nullptr;
+    const int form = grouped_form(method, variant, schedule, L);
+    std::vector<TileRef> table;
+    if (form == kFormStream) build_tile_table(L, &table);
+    // device buffer: descriptors | split jobs | work counters | tile table | split workspace
     const size_t desc_bytes = align256(nd * sizeof(GroupedDesc));
     const size_t job_bytes = align256(L.jobs.size() * sizeof(SplitJob) + 1);
-    const size_t total = desc_bytes + job_bytes + 256 + L.ws_bytes;
-    MM_HIP(hipMallocAsync((void **)&buf, total, st));
-    char *ws = buf + desc_bytes + job_bytes + 256;
-    build_layout(probs, order, method, variant, ws, &L);
+    const size_t counter_bytes = 256;
+    const size_t table_bytes = align256(table.size() * sizeof(TileRef));
+    const size_t ws_offset = desc_bytes + job_bytes + counter_bytes + table_bytes;
+    char *buf = nullptr;
+    MM_HIP(hipMallocAsync((void **)&buf, ws_offset + L.ws_bytes, st));
+    build_layout(probs, order, method, variant, buf + ws_offset, &L);
     GroupedDesc *d_descs = (GroupedDesc *)buf;
     SplitJob *d_jobs = (SplitJob *)(buf + desc_bytes);
     int *d_counter = schedule == 2 ? (int *)(buf + desc_bytes + job_bytes) : nullptr;
-    // descriptors then jobs, as laid out in buf
-    mm_status s = upload_staged(buf, L.descs.data(), nd * sizeof(GroupedDesc), desc_bytes, L.jobs.data(),
-                                L.jobs.size() * sizeof(SplitJob), st);
+    const size_t table_offset = desc_bytes + job_bytes + counter_bytes;
+    TileRef *d_tiles = table.empty() ? nullptr : (TileRef *)(buf + table_offset);
+    const Piece pieces[] = {{0, L.descs.data(), nd * sizeof(GroupedDesc)},
+                            {desc_bytes, L.jobs.data(), L.jobs.size() * sizeof(SplitJob)},
+                            {table_offset, table.data(), table.size() * sizeof(TileRef)}};
+    mm_status s = upload_staged(buf, pieces, 3, st);
     hipError_t e = hipSuccess;
     if (s == MM_OK)
-        e = grouped_enqueue(method, variant, schedule != 3, d_descs, (int)nd, L.total_tiles, d_jobs, (int)L.jobs.size(),
-                            L.split_tiles, d_counter, st);
+        e = grouped_enqueue(method, variant, form, d_descs, (int)nd, L.total_tiles, d_jobs, (int)L.jobs.size(),
+                            L.split_tiles, d_counter, d_tiles, st);
     hipError_t e2 = hipFreeAsync(buf, st);
     if (s != MM_OK) return s;
     if (e == hipSuccess) e = e2;
@@ -695,10 +876,8 @@ mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out
     if (schedule_out) *schedule_out = plan->schedule;
     if (tiles_out) *tiles_out = plan->layout.total_tiles;
     if (grid_out) {
-        const KernelInfo k = kernel_for(plan->method, plan->variant);
-        int64_t g = plan->schedule == 3 ? chunked_grid(plan->layout.total_tiles)
-                                        : persistent_grid(plan->method, plan->variant, k.fn, k.nt);
-        if (plan->schedule != 3 && g > plan->layout.total_tiles) g = plan->layout.total_tiles;
+        const int form = grouped_form(plan->method, plan->variant, plan->schedule, plan->layout);
+        const int64_t g = launch_grid(form, kernel_for(plan->method, plan->variant, form), plan->layout.total_tiles);
         *grid_out = (int32_t)(g < 0x7fffffffLL ? g : 0x7fffffffLL);
     }
     if (uses_graph_out) *uses_graph_out = plan->exec != nullptr;

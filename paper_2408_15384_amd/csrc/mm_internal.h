@@ -143,6 +143,12 @@ struct SplitJob {
     int32_t pad;
 };
 
+// Owner problem and tile coordinates of one tile of a grouped batch (the
+// streamed form reads these instead of searching the prefix sums).
+struct TileRef {
+    int32_t own, tm, tn, pad;
+};
+
 // Host tile map of one grouped batch.
 struct Layout {
     std::vector<GroupedDesc> descs;
@@ -150,6 +156,7 @@ struct Layout {
     int64_t total_tiles = 0;
     int64_t split_tiles = 0;
     size_t ws_bytes = 0;  // split planes of the whole batch
+    bool ring_ok = true;  // every problem fits the ring-fused tiles' 31-bit lane offsets
 };
 
 int grouped_tile_bm(mm_method method, int variant);
@@ -161,10 +168,20 @@ std::vector<int> schedule_order(const mm_problem *probs, int count, int schedule
 // tiled by `variant`; empty problems are dropped.
 void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_method method, int variant,
                   char *ws, Layout *L);
+// Kernel forms of a grouped launch: one workgroup per tile (schedule 3), a
+// persistent grid looping over tiles (schedules 0-2), or, for the ring-fused
+// split tiles when every problem fits them, the streamed persistent grid
+// (schedules 0-2; schedule 2 draws tiles from the work counter).
+constexpr int kFormTile = 0, kFormPersistent = 1, kFormStream = 2;
+int grouped_form(mm_method method, int variant, int schedule, const Layout &L);
+// Tile table of a layout, in tile-id order (for the streamed form).
+void build_tile_table(const Layout &L, std::vector<TileRef> *out);
 // Enqueue [grouped split pass] -> [counter reset] -> grouped GEMM for
 // descriptors already in device memory.
-hipError_t grouped_enqueue(mm_method method, int variant, bool persistent, const GroupedDesc *d_descs, int ndesc, int64_t total_tiles,
-                           const SplitJob *d_jobs, int njobs, int64_t split_tiles, int *d_counter, hipStream_t st);
+// d_tiles: the layout's tile table on the device (streamed form only, else null).
+hipError_t grouped_enqueue(mm_method method, int variant, int form, const GroupedDesc *d_descs, int ndesc, int64_t total_tiles,
+                           const SplitJob *d_jobs, int njobs, int64_t split_tiles, int *d_counter,
+                           const TileRef *d_tiles, hipStream_t st);
 // Keep memory freed by hipFreeAsync in the device's default pool.
 void retain_default_pool();
 

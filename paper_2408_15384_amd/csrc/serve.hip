@@ -220,8 +220,8 @@ static mm_status launch(mm_server *s, Slot &slot, const std::vector<uint64_t> &i
         // of other slots interleave with it workgroup by workgroup (measured
         // p50/p99 0.40/3.1-3.4 ms against 0.45/3.4-3.9 ms for a persistent
         // grid pulling from a work counter, at 20k requests/s)
-        MM_HIP(grouped_enqueue(m, variant, false, dd, (int)L[g].descs.size(), L[g].total_tiles, dj, (int)L[g].jobs.size(),
-                               L[g].split_tiles, nullptr, slot.stream));
+        MM_HIP(grouped_enqueue(m, variant, kFormTile, dd, (int)L[g].descs.size(), L[g].total_tiles, dj, (int)L[g].jobs.size(),
+                               L[g].split_tiles, nullptr, nullptr, slot.stream));
     }
     MM_HIP(hipEventRecord(slot.done, slot.stream));
     return MM_OK;

@@ -691,12 +691,383 @@ struct SplitTileFused : SplitTile<NPROD, BM_, BN_, 32, WM_, WN_, 1> {
     }
 };
 
+// ---------------------------------------------------------------------------
+// Fused form with a register ring and buffer loads.  The same planes, LDS
+// layout, MFMA sequence and recombination as SplitTileFused (so the same
+// bits), with a cheaper and deeper load side:
+//  * loads are raw buffer loads through a resource based at the K step's
+//    slice (scalar), each lane's byte offsets computed once per tile, so a K
+//    step spends no vector instructions on addresses;
+//  * entries past the matrix read as zero without vector masking: rows of A
+//    past M and columns of B past N get an offset beyond the resource's
+//    range (the hardware returns zero for those), as do rows of B past K
+//    (they lie beyond the last valid byte); only the A columns past K of
+//    the last K step are cleared in registers;
+//  * RS K steps are in flight in registers: step kt + RS is requested while
+//    step kt is multiplied;
+//  * bfloat16 planes are made two values at a time (one packed convert per
+//    pair, the pair's leftovers by subtraction).
+// Tiles whose per-lane offsets would not fit 31 bits run SplitTileFused.
+template <int NPROD, int BM_, int BN_, int WM_, int WN_, int RS_>
+struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
+    using Fused = SplitTileFused<NPROD, BM_, BN_, WM_, WN_>;
+    using Base = typename Fused::Base;
+    static constexpr bool FUSED = true;
+    using Base::BM; using Base::BN; using Base::BK; using Base::WM; using Base::WN;
+    using Base::NP; using Base::NWN; using Base::NWAVES; using Base::NT; using Base::FM; using Base::FN;
+    using Base::LD; using Base::A_PLANE; using Base::B_PLANE; using Base::STAGE; using Base::LDS_ELEMS;
+    static constexpr int RS = RS_;
+    static constexpr int CHUNKS = BK / 8;                // 8-element units per 32-wide row
+    static constexpr int A_UNITS = BM * CHUNKS / NT;
+    static constexpr int B_UNITS = BN * CHUNKS / NT;
+    static_assert(RS >= 1 && RS <= 4, "register stages");
+    static_assert((BM * CHUNKS) % NT == 0 && (BN * CHUNKS) % NT == 0, "units must split evenly");
+    // byte offset that lies beyond every resource range used here
+    static constexpr uint32_t OOB = 0x80000000u;
+
+    struct Regs {
+        f32x4 a[A_UNITS][2];
+        float b[B_UNITS][8];
+    };
+
+    // Per-lane byte offsets of one tile (relative to the K step's slice).
+    struct Offs {
+        uint32_t a[A_UNITS];
+        uint32_t b[B_UNITS][8];
+    };
+
+    static __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const float *base, int64_t bytes) {
+        const int32_t n = bytes <= 0 ? 0 : (bytes >= 0x7fffffff ? 0x7fffffff : (int32_t)bytes);
+        return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, n, 0x00020000);
+    }
+
+    // Whether the tile's lane offsets fit (wave-uniform).
+    static __device__ __forceinline__ bool ring_ok(int64_t lda, int64_t ldb) {
+        return ((int64_t)(BM - 1) * lda + BK) * 4 < 0x7fff0000LL && ((int64_t)(BK - 1) * ldb + BN) * 4 < 0x7fff0000LL;
+    }
+
+    static __device__ __forceinline__ void offsets(int64_t lda, int64_t ldb, int rows_left, int cols_left, Offs &o) {
+#pragma unroll
+        for (int i = 0; i < A_UNITS; ++i) {
+            const int u = threadIdx.x + i * NT;
+            const int r = u / CHUNKS, c = u % CHUNKS;
+            o.a[i] = r < rows_left ? (uint32_t)(((int64_t)r * lda + c * 8) * 4) : OOB;
+        }
+#pragma unroll
+        for (int i = 0; i < B_UNITS; ++i) {
+            const int u = threadIdx.x + i * NT;
+            const int n = u % BN, kc = u / BN;
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                o.b[i][e] = n < cols_left ? (uint32_t)(((int64_t)(kc * 8 + e) * ldb + n) * 4) : OOB;
+        }
+    }
+
+    // Request K step kt of the tile whose A panel starts at Ap (row m0) and B
+    // panel at Bp (column n0).
+    static __device__ __forceinline__ void load(Regs &R, const Offs &o, const float *Ap, int64_t lda, const float *Bp,
+                                                int64_t ldb, int rows_left, int cols_left, int64_t K, int64_t kt) {
+        const int64_t k0 = kt * BK;
+        const __amdgpu_buffer_rsrc_t ra = rsrc(Ap + k0, ((int64_t)(rows_left - 1) * lda + (K - k0)) * 4);
+        const __amdgpu_buffer_rsrc_t rb = rsrc(Bp + k0 * ldb, ((K - 1 - k0) * ldb + cols_left) * 4);
+#pragma unroll
+        for (int i = 0; i < A_UNITS; ++i) {
+            R.a[i][0] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, o.a[i], 0, 0));
+            R.a[i][1] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(ra, o.a[i] + 16, 0, 0));
+        }
+#pragma unroll
+        for (int i = 0; i < B_UNITS; ++i)
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                R.b[i][e] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, o.b[i][e], 0, 0));
+    }
+
+    // bfloat16 planes of 8 values, two at a time: one packed round-to-nearest-
+    // even convert per pair, the leftovers formed exactly in FP32.
+    static __device__ __forceinline__ void put8(uint16_t *base, int plane_elems, int row, int chunk, float (&x)[8]) {
+        typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+        typedef float f32x2 __attribute__((ext_vector_type(2)));
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+            u32x4 w;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                const bf16x2 hb = __builtin_convertvector((f32x2){x[2 * h], x[2 * h + 1]}, bf16x2);
+                const uint32_t bits = __builtin_bit_cast(uint32_t, hb);
+                w[h] = bits;
+                if (p + 1 < NP) {
+                    x[2 * h] -= __builtin_bit_cast(float, bits << 16);
+                    x[2 * h + 1] -= __builtin_bit_cast(float, bits & 0xffff0000u);
+                }
+            }
+            *reinterpret_cast<u32x4 *>(base + p * plane_elems + row * LD + Base::swz(row, chunk) * 8) = w;
+        }
+    }
+
+    // Split the step held in R and write its planes to LDS; `kvalid` is the
+    // number of valid K entries of the step (the A columns past it are
+    // cleared; B rows past K already read as zero).
+    static __device__ __forceinline__ void put(uint16_t *stage, const Regs &R, int64_t kvalid) {
+        if (kvalid <= 0) {
+            // the single step of a tile without K entries: all planes zero
+            float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int i = 0; i < A_UNITS; ++i) {
+                const int u = threadIdx.x + i * NT;
+                put8(stage, A_PLANE, u / CHUNKS, u % CHUNKS, z);
+            }
+#pragma unroll
+            for (int i = 0; i < B_UNITS; ++i) {
+                const int u = threadIdx.x + i * NT;
+                put8(stage + NP * A_PLANE, B_PLANE, u % BN, u / BN, z);
+            }
+            return;
+        }
+#pragma unroll
+        for (int i = 0; i < A_UNITS; ++i) {
+            const int u = threadIdx.x + i * NT;
+            float x[8];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                x[e] = R.a[i][0][e];
+                x[4 + e] = R.a[i][1][e];
+            }
+            if (kvalid < BK) {
+                const int c0 = (u % CHUNKS) * 8;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = c0 + e < kvalid ? x[e] : 0.f;
+            }
+            put8(stage, A_PLANE, u / CHUNKS, u % CHUNKS, x);
+        }
+#pragma unroll
+        for (int i = 0; i < B_UNITS; ++i) {
+            const int u = threadIdx.x + i * NT;
+            float x[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = R.b[i][e];
+            put8(stage + NP * A_PLANE, B_PLANE, u % BN, u / BN, x);
+        }
+    }
+
+    static __device__ __forceinline__ void epilogue(const f32x4 (&lead)[FM][FN], const f32x4 (&corr)[FM][FN], void *C,
+                                                    int64_t ldc, int c_is_f64, int64_t M, int64_t N, int64_t m0,
+                                                    int64_t n0) {
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int wm = wave / NWN, wn = wave % NWN;
+        const int li = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int64_t r = m0 + wm * WM + fm * 16 + q * 4 + v;
+                    const int64_t c = n0 + wn * WN + fn * 16 + li;
+                    if (r < M && c < N) {
+                        const double val = (double)lead[fm][fn][v] + (double)corr[fm][fn][v];
+                        if (c_is_f64) ((gptr<double>)(double *)C)[r * ldc + c] = val;
+                        else ((gptr<float>)(float *)C)[r * ldc + c] = (float)val;
+                    }
+                }
+    }
+
+    // Tile (tm, tn) of C = A.B, same contract as SplitTileFused::run_fused.
+    static __device__ __forceinline__ void run_fused(const float *A, int64_t lda, const float *B, int64_t ldb,
+                                                     void *C, int64_t ldc, int c_is_f64, int64_t M, int64_t N,
+                                                     int64_t K, int64_t tm, int64_t tn, uint16_t *smem) {
+        if (!ring_ok(lda, ldb)) {
+            Fused::run_fused(A, lda, B, ldb, C, ldc, c_is_f64, M, N, K, tm, tn, smem);
+            return;
+        }
+        const int64_t m0 = tm * BM, n0 = tn * BN;
+        const int rows_left = (int)((M - m0) < BM ? (M - m0) : BM);
+        const int cols_left = (int)((N - n0) < BN ? (N - n0) : BN);
+        const float *Ap = A + m0 * lda, *Bp = B + n0;
+        f32x4 lead[FM][FN], corr[FM][FN];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) {
+                lead[fm][fn] = f32x4{0, 0, 0, 0};
+                corr[fm][fn] = f32x4{0, 0, 0, 0};
+            }
+        const int64_t nkt = (K + BK - 1) / BK;
+        if (nkt > 0) {
+            Offs o;
+            offsets(lda, ldb, rows_left, cols_left, o);
+            Regs R[RS];
+#pragma unroll
+            for (int r = 0; r < RS; ++r)
+                if (r < nkt) load(R[r], o, Ap, lda, Bp, ldb, rows_left, cols_left, K, r);
+            put(smem, R[0], K);
+            __syncthreads();
+            for (int64_t s = 0; s < nkt; s += RS) {
+#pragma unroll
+                for (int r = 0; r < RS; ++r) {
+                    const int64_t kt = s + r;
+                    if (kt < nkt) {
+                        // slot r held step kt (already in LDS): refill it with kt + RS
+                        if (kt + RS < nkt) load(R[r], o, Ap, lda, Bp, ldb, rows_left, cols_left, K, kt + RS);
+                        const uint16_t *cur = smem + (kt & 1) * STAGE;
+                        Base::compute(cur, cur + NP * A_PLANE, lead, corr);
+                        if (kt + 1 < nkt) put(smem + ((kt + 1) & 1) * STAGE, R[(r + 1) % RS], K - (kt + 1) * BK);
+                        __syncthreads();
+                    }
+                }
+            }
+        }
+        epilogue(lead, corr, C, ldc, c_is_f64, M, N, m0, n0);
+    }
+
+    // ---------------------------------------------------------------- stream
+    // A persistent workgroup's tiles as one stream of K steps: the load side
+    // runs RS steps ahead of the products and crosses into the next tile
+    // while the current one is still being multiplied, so a tile's first
+    // loads are in flight when its predecessor ends.  Each tile's products,
+    // order and recombination are those of run_fused (the same bits).
+    // `seq` names the workgroup's i-th tile (seq.tile(i), >= total at the end;
+    // seq.draw(i) is called once the i-th tile is opened for loading, so that
+    // a dynamic sequence can fetch the (i+1)-th).  decode(t, g) fills tile t's
+    // geometry; every tile must satisfy ring_ok (the caller checks the batch).
+    // A tile without K steps (K == 0) runs one step of zeros.
+    struct Geo {
+        const float *A, *B;
+        void *C;
+        int64_t lda, ldb, ldc, M, N, K, tm, tn;
+    };
+
+    struct LoadCursor {
+        const float *Ap, *Bp;
+        int64_t lda, ldb, K, nk, k, t;
+        int rows_left, cols_left, i;
+        Offs o;
+    };
+
+    struct ComputeCursor {
+        void *C;
+        int64_t ldc, M, N, m0, n0, nk, k, t;
+        int i;
+    };
+
+    static __device__ __forceinline__ int64_t steps_of(int64_t K) { return K > 0 ? (K + BK - 1) / BK : 1; }
+
+    template <typename Seq, typename Decode>
+    static __device__ __forceinline__ void open_load(LoadCursor &L, int i, int64_t total, Seq &seq, Decode &decode) {
+        L.i = i;
+        L.t = seq.tile(i);
+        if (L.t >= total) return;
+        seq.draw(i);
+        Geo g;
+        decode(L.t, g);
+        const int64_t m0 = g.tm * BM, n0 = g.tn * BN;
+        L.Ap = g.A + m0 * g.lda;
+        L.Bp = g.B + n0;
+        L.lda = g.lda;
+        L.ldb = g.ldb;
+        L.K = g.K;
+        L.nk = steps_of(g.K);
+        L.k = 0;
+        L.rows_left = (int)((g.M - m0) < BM ? (g.M - m0) : BM);
+        L.cols_left = (int)((g.N - n0) < BN ? (g.N - n0) : BN);
+        offsets(L.lda, L.ldb, L.rows_left, L.cols_left, L.o);
+    }
+
+    // Request the load cursor's next step into R (kvalid: valid K entries of
+    // that step, 0 for the zero step of a K == 0 tile) and advance.
+    template <typename Seq, typename Decode>
+    static __device__ __forceinline__ void next_load(LoadCursor &L, Regs &R, int64_t &kvalid, int64_t total, Seq &seq,
+                                                     Decode &decode) {
+        if (L.t >= total) return;
+        if (L.K > 0) {
+            load(R, L.o, L.Ap, L.lda, L.Bp, L.ldb, L.rows_left, L.cols_left, L.K, L.k);
+            kvalid = L.K - L.k * BK;
+        } else {
+            kvalid = 0;
+        }
+        if (++L.k == L.nk) open_load(L, L.i + 1, total, seq, decode);
+    }
+
+    template <typename Seq, typename Decode>
+    static __device__ __forceinline__ bool open_compute(ComputeCursor &Cc, int i, int64_t total, Seq &seq,
+                                                        Decode &decode) {
+        Cc.i = i;
+        Cc.t = seq.tile(i);
+        if (Cc.t >= total) return false;
+        Geo g;
+        decode(Cc.t, g);
+        Cc.C = g.C;
+        Cc.ldc = g.ldc;
+        Cc.M = g.M;
+        Cc.N = g.N;
+        Cc.m0 = g.tm * BM;
+        Cc.n0 = g.tn * BN;
+        Cc.nk = steps_of(g.K);
+        Cc.k = 0;
+        return true;
+    }
+
+    template <typename Seq, typename Decode>
+    static __device__ __forceinline__ void run_stream(int64_t total, int c_is_f64, Seq seq, Decode decode,
+                                                      uint16_t *smem) {
+        f32x4 lead[FM][FN], corr[FM][FN];
+#pragma unroll
+        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) {
+                lead[fm][fn] = f32x4{0, 0, 0, 0};
+                corr[fm][fn] = f32x4{0, 0, 0, 0};
+            }
+        ComputeCursor Cc;
+        if (!open_compute(Cc, 0, total, seq, decode)) return;
+        LoadCursor L;
+        open_load(L, 0, total, seq, decode);
+        Regs R[RS];
+        int64_t kv[RS];
+#pragma unroll
+        for (int r = 0; r < RS; ++r) {
+            kv[r] = 0;
+            next_load(L, R[r], kv[r], total, seq, decode);
+        }
+        put(smem, R[0], kv[0]);
+        __syncthreads();
+        bool live = true;
+        for (int64_t g = 0; live; g += RS) {
+#pragma unroll
+            for (int r = 0; r < RS; ++r) {
+                if (live) {
+                    // stream step g + r is in LDS buffer (g + r) & 1; slot r is free
+                    next_load(L, R[r], kv[r], total, seq, decode);
+                    const uint16_t *cur = smem + ((g + r) & 1) * STAGE;
+                    Base::compute(cur, cur + NP * A_PLANE, lead, corr);
+                    if (++Cc.k == Cc.nk) {
+                        epilogue(lead, corr, Cc.C, Cc.ldc, c_is_f64, Cc.M, Cc.N, Cc.m0, Cc.n0);
+#pragma unroll
+                        for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                            for (int fn = 0; fn < FN; ++fn) {
+                                lead[fm][fn] = f32x4{0, 0, 0, 0};
+                                corr[fm][fn] = f32x4{0, 0, 0, 0};
+                            }
+                        live = open_compute(Cc, Cc.i + 1, total, seq, decode);
+                    }
+                    if (live) put(smem + ((g + r + 1) & 1) * STAGE, R[(r + 1) % RS], kv[(r + 1) % RS]);
+                    __syncthreads();
+                }
+            }
+        }
+    }
+};
+
 // Variant selector: S = 1, 2 register stages (SplitTile); S = 10 + b: direct
 // global-to-LDS ring of b buffers (SplitTileDirect, BK = 32); S = 20: fused
-// split (SplitTileFused, BK = 32, FP32 operands, no plane pass).
+// split (SplitTileFused, BK = 32, FP32 operands, no plane pass); S = 20 + r
+// (r = 1..4): the fused split with buffer loads and r K steps in flight in
+// registers (SplitTileFusedRing).
 // IL asks the direct tile of the 2-plane method for interleaved planes.
 template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool IL = false,
-          int KIND = (S >= 20 ? 2 : S >= 10 ? 1 : 0)>
+          int KIND = (S > 20 ? 3 : S == 20 ? 2 : S >= 10 ? 1 : 0)>
 struct SplitTileSel {
     typedef SplitTile<NPROD, BM, BN, BK, WM, WN, S> type;
 };
@@ -708,6 +1079,11 @@ template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool IL>
 struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, IL, 2> {
     static_assert(BK == 32, "the fused tile steps K by 32");
     typedef SplitTileFused<NPROD, BM, BN, WM, WN> type;
+};
+template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool IL>
+struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, IL, 3> {
+    static_assert(BK == 32, "the fused tile steps K by 32");
+    typedef SplitTileFusedRing<NPROD, BM, BN, WM, WN, S - 20> type;
 };
 
 }  // namespace mm

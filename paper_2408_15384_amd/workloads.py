@@ -3,6 +3,7 @@ output holds only their kernels.
 
     python -m paper_2408_15384_amd.workloads grouped --method split6 [--variant V --schedule S] [--reps 5]
     python -m paper_2408_15384_amd.workloads gemm --method f64 --n 8192 [--variant V] [--reps 5]
+    (--sweep V:S,V:S,... or V,V,... times several configurations in one run)
 
 grouped: the 512-problem batch (M, N, K each log-uniform on [32, 1024], seed 0,
 FP32 entries uniform on [-1, 1)), one plan captured with the given tile variant
@@ -34,7 +35,7 @@ def _events(torch, fn, reps, warmup=1):
     return e0.elapsed_time(e1) / reps
 
 
-def grouped(method, variant, schedule, reps):
+def grouped(method, variant, schedule, reps, sweep=None):
     import torch
     from paper_2408_15384_amd import api, inputs as I
     api.load_library()
@@ -46,16 +47,18 @@ def grouped(method, variant, schedule, reps):
         As.append(torch.from_numpy(A).cuda())
         Bs.append(torch.from_numpy(B).cuda())
         Cs.append(torch.empty((M, N), dtype=torch.float32, device="cuda"))
-    plan = api.GroupedPlan(method, variant, schedule)
-    plan.run(As, Bs, Cs)
-    ms = _events(torch, plan.replay, reps)
-    info = plan.info()
-    plan.close()
-    print(f"grouped {method} variant {info['variant']} schedule {info['schedule']} tiles {info['tiles']}: "
-          f"{ms:.4f} ms per replay", flush=True)
+    configs = [(variant, schedule)] if not sweep else [tuple(int(x) for x in c.split(":")) for c in sweep.split(",")]
+    for v, s in configs:
+        plan = api.GroupedPlan(method, v, s)
+        plan.run(As, Bs, Cs)
+        ms = _events(torch, plan.replay, reps)
+        info = plan.info()
+        plan.close()
+        print(f"grouped {method} variant {info['variant']} schedule {info['schedule']} tiles {info['tiles']}: "
+              f"{ms:.4f} ms per replay", flush=True)
 
 
-def gemm(method, n, variant, reps):
+def gemm(method, n, variant, reps, sweep=None):
     import torch
     from paper_2408_15384_amd import api, inputs as I
     api.load_library()
@@ -68,11 +71,12 @@ def gemm(method, n, variant, reps):
     ws = None
     if method in ("split3", "split6"):
         ws = torch.empty(api.split_workspace_bytes(n, n, n, 6), dtype=torch.uint8, device="cuda")
-    if variant is None:
-        variant = api.select_variant(method, n, n, n)
-    ms = _events(torch, lambda: api.gemm_variant(method, variant, dA, dB, C, workspace=ws), reps)
-    print(f"gemm {method} n={n} variant {variant}: {ms:.4f} ms per launch, "
-          f"{2.0 * n ** 3 / (ms * 1e-3) / 1e12:.1f} TFLOP/s", flush=True)
+    variants = [int(x) for x in sweep.split(",")] if sweep else [
+        variant if variant is not None else api.select_variant(method, n, n, n)]
+    for v in variants:
+        ms = _events(torch, lambda: api.gemm_variant(method, v, dA, dB, C, workspace=ws), reps)
+        print(f"gemm {method} n={n} variant {v}: {ms:.4f} ms per launch, "
+              f"{2.0 * n ** 3 / (ms * 1e-3) / 1e12:.1f} TFLOP/s", flush=True)
 
 
 def main(argv=None):
@@ -83,13 +87,15 @@ def main(argv=None):
     ap.add_argument("--schedule", type=int, default=None)
     ap.add_argument("--n", type=int, default=8192)
     ap.add_argument("--reps", type=int, default=5)
+    ap.add_argument("--sweep", default=None,
+                    help="grouped: comma list of variant:schedule pairs; gemm: comma list of variants")
     a = ap.parse_args(argv)
     if a.workload == "grouped":
         if a.method == "f64":
             ap.error("the grouped batch has FP32 inputs: --method f32, split3 or split6")
-        grouped(a.method, a.variant, a.schedule, a.reps)
+        grouped(a.method, a.variant, a.schedule, a.reps, a.sweep)
     else:
-        gemm(a.method, a.n, a.variant, a.reps)
+        gemm(a.method, a.n, a.variant, a.reps, a.sweep)
 
 
 if __name__ == "__main__":
