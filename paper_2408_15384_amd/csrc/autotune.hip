@@ -68,13 +68,13 @@ const Candidate kF32Cand[] = {{12, 256, 128, 141.7, false}, {3, 128, 128, 126.5,
                               {10, 32, 32, 95.0, false}};
 const Candidate kSplit3Unfused[] = {{14, 256, 128, 438.0, true}, {6, 128, 128, 364.0, true}, {8, 64, 64, 319.0, true}};
 const Candidate kSplit6Unfused[] = {{9, 256, 128, 214.0, true}, {6, 128, 128, 190.0, true}, {8, 64, 64, 100.4, true}};
-// Fused candidates are the ring forms with one K step in flight (64x64 and
-// 128x64; rates at 8192 on MI355X), which replaced the register-staged fused
-// tiles at every size measured (512 ... 8192).
+// Fused candidates are the ring forms with one K step in flight and paired
+// LDS lines (64x64 and 128x64; rates at 8192 on MI355X), which replaced the
+// register-staged fused tiles at every size measured (512 ... 8192).
 const Candidate kSplit3Cand[] = {{14, 256, 128, 438.0, true}, {6, 128, 128, 364.0, true}, {8, 64, 64, 319.0, true},
-                                 {20, 64, 64, 225.3, false},  {21, 128, 64, 253.9, false}};
+                                 {15, 64, 64, 236.0, false},  {16, 128, 64, 265.0, false}};
 const Candidate kSplit6Cand[] = {{9, 256, 128, 214.0, true}, {6, 128, 128, 190.0, true}, {8, 64, 64, 100.4, true},
-                                 {20, 64, 64, 146.5, false}, {21, 128, 64, 159.9, false}};
+                                 {15, 64, 64, 154.6, false}, {16, 128, 64, 166.7, false}};
 
 constexpr double kCUs = 256.0;
 
@@ -147,7 +147,7 @@ int select_grouped(const mm_problem *probs, int count, mm_method method, int *sc
     switch (method) {
         case MM_F64: return 6;
         case MM_F32: return 8;
-        default: return 20;
+        default: return 15;
     }
 }
 

@@ -708,7 +708,7 @@ struct SplitTileFused : SplitTile<NPROD, BM_, BN_, 32, WM_, WN_, 1> {
 //  * bfloat16 planes are made two values at a time (one packed convert per
 //    pair, the pair's leftovers by subtraction).
 // Tiles whose per-lane offsets would not fit 31 bits run SplitTileFused.
-template <int NPROD, int BM_, int BN_, int WM_, int WN_, int RS_>
+template <int NPROD, int BM_, int BN_, int WM_, int WN_, int RS_, bool PAIRED_ = false>
 struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
     using Fused = SplitTileFused<NPROD, BM_, BN_, WM_, WN_>;
     using Base = typename Fused::Base;
@@ -717,7 +717,50 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
     using Base::NP; using Base::NWN; using Base::NWAVES; using Base::NT; using Base::FM; using Base::FN;
     using Base::LD; using Base::A_PLANE; using Base::B_PLANE; using Base::STAGE; using Base::LDS_ELEMS;
     static constexpr int RS = RS_;
+    // PAIRED: rows r and r + 8 of each 16-row group share one 128-byte LDS
+    // line (chunk ^ (row/2 mod 4)), so the 16 rows of a fragment read cover
+    // all banks once; otherwise SplitTile's 64-byte rows.
+    static constexpr bool PAIRED = PAIRED_;
     static constexpr int CHUNKS = BK / 8;                // 8-element units per 32-wide row
+
+    // Element offset of (row, 16-byte chunk) within a plane.
+    static __device__ __forceinline__ int lds_elem(int row, int chunk) {
+        if constexpr (PAIRED)
+            return (row >> 4) * 512 + (row & 7) * 64 + ((row >> 3) & 1) * 32 + ((chunk ^ ((row >> 1) & 3)) * 8);
+        return row * LD + Base::swz(row, chunk) * 8;
+    }
+
+    static __device__ __forceinline__ bf16x8 frag(const uint16_t *plane, int row, int chunk) {
+        return __builtin_bit_cast(bf16x8, *reinterpret_cast<const u16x8 *>(plane + lds_elem(row, chunk)));
+    }
+
+    // The products of one K step: SplitTile::compute's sequence (terms in
+    // order, two accumulator sets) on this tile's LDS layout.
+    static __device__ __forceinline__ void compute(const uint16_t *As, const uint16_t *Bs, f32x4 (&lead)[FM][FN],
+                                                   f32x4 (&corr)[FM][FN]) {
+        using Terms = typename Base::Terms;
+        const int lane = threadIdx.x & 63;
+        const int wave = threadIdx.x >> 6;
+        const int wm = wave / NWN, wn = wave % NWN;
+        const int li = lane & 15, q = lane >> 4;
+#pragma unroll
+        for (int t = 0; t < Terms::n; ++t) {
+            bf16x8 a[FM], b[FN];
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm) a[fm] = frag(As + Terms::pa[t] * A_PLANE, wm * WM + fm * 16 + li, q);
+#pragma unroll
+            for (int fn = 0; fn < FN; ++fn) b[fn] = frag(Bs + Terms::pb[t] * B_PLANE, wn * WN + fn * 16 + li, q);
+#pragma unroll
+            for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                for (int fn = 0; fn < FN; ++fn) {
+                    if (t == 0)
+                        lead[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[fm], b[fn], lead[fm][fn], 0, 0, 0);
+                    else
+                        corr[fm][fn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[fm], b[fn], corr[fm][fn], 0, 0, 0);
+                }
+        }
+    }
     static constexpr int A_UNITS = BM * CHUNKS / NT;
     static constexpr int B_UNITS = BN * CHUNKS / NT;
     static_assert(RS >= 1 && RS <= 4, "register stages");
@@ -801,39 +844,29 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
                     x[2 * h + 1] -= __builtin_bit_cast(float, bits & 0xffff0000u);
                 }
             }
-            *reinterpret_cast<u32x4 *>(base + p * plane_elems + row * LD + Base::swz(row, chunk) * 8) = w;
+            *reinterpret_cast<u32x4 *>(base + p * plane_elems + lds_elem(row, chunk)) = w;
         }
     }
 
     // Split the step held in R and write its planes to LDS; `kvalid` is the
     // number of valid K entries of the step (the A columns past it are
     // cleared; B rows past K already read as zero).
-    static __device__ __forceinline__ void put(uint16_t *stage, const Regs &R, int64_t kvalid) {
-        if (kvalid <= 0) {
-            // the single step of a tile without K entries: all planes zero
-            float z[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-            for (int i = 0; i < A_UNITS; ++i) {
-                const int u = threadIdx.x + i * NT;
-                put8(stage, A_PLANE, u / CHUNKS, u % CHUNKS, z);
-            }
-#pragma unroll
-            for (int i = 0; i < B_UNITS; ++i) {
-                const int u = threadIdx.x + i * NT;
-                put8(stage + NP * A_PLANE, B_PLANE, u % BN, u / BN, z);
-            }
-            return;
-        }
+    // Split one K step held in R and write its planes to LDS.  MODE 0: a
+    // whole step; 1: the A columns at or past `kvalid` are cleared (the last
+    // step of a tile whose K is not a multiple of 32; B rows past K already
+    // read as zero); 2: all planes zero (the single step of a tile without K).
+    template <int MODE>
+    static __device__ __forceinline__ void put_mode(uint16_t *stage, const Regs &R, int kvalid) {
 #pragma unroll
         for (int i = 0; i < A_UNITS; ++i) {
             const int u = threadIdx.x + i * NT;
             float x[8];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                x[e] = R.a[i][0][e];
-                x[4 + e] = R.a[i][1][e];
+                x[e] = MODE == 2 ? 0.f : R.a[i][0][e];
+                x[4 + e] = MODE == 2 ? 0.f : R.a[i][1][e];
             }
-            if (kvalid < BK) {
+            if constexpr (MODE == 1) {
                 const int c0 = (u % CHUNKS) * 8;
 #pragma unroll
                 for (int e = 0; e < 8; ++e) x[e] = c0 + e < kvalid ? x[e] : 0.f;
@@ -845,9 +878,18 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
             const int u = threadIdx.x + i * NT;
             float x[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) x[e] = R.b[i][e];
+            for (int e = 0; e < 8; ++e) x[e] = MODE == 2 ? 0.f : R.b[i][e];
             put8(stage + NP * A_PLANE, B_PLANE, u % BN, u / BN, x);
         }
+    }
+
+    // `kvalid`: valid K entries of the step (at least BK for a whole step).
+    // Each case is a complete put of its own, so the common whole-step path
+    // carries no masking work and no register copies from a join.
+    static __device__ __forceinline__ void put(uint16_t *stage, const Regs &R, int64_t kvalid) {
+        if (kvalid >= BK) put_mode<0>(stage, R, BK);
+        else if (kvalid > 0) put_mode<1>(stage, R, (int)kvalid);
+        else put_mode<2>(stage, R, 0);
     }
 
     static __device__ __forceinline__ void epilogue(const f32x4 (&lead)[FM][FN], const f32x4 (&corr)[FM][FN], void *C,
@@ -911,7 +953,7 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
                         // slot r held step kt (already in LDS): refill it with kt + RS
                         if (kt + RS < nkt) load(R[r], o, Ap, lda, Bp, ldb, rows_left, cols_left, K, kt + RS);
                         const uint16_t *cur = smem + (kt & 1) * STAGE;
-                        Base::compute(cur, cur + NP * A_PLANE, lead, corr);
+                        compute(cur, cur + NP * A_PLANE, lead, corr);
                         if (kt + 1 < nkt) put(smem + ((kt + 1) & 1) * STAGE, R[(r + 1) % RS], K - (kt + 1) * BK);
                         __syncthreads();
                     }
@@ -1040,7 +1082,7 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
                     // stream step g + r is in LDS buffer (g + r) & 1; slot r is free
                     next_load(L, R[r], kv[r], total, seq, decode);
                     const uint16_t *cur = smem + ((g + r) & 1) * STAGE;
-                    Base::compute(cur, cur + NP * A_PLANE, lead, corr);
+                    compute(cur, cur + NP * A_PLANE, lead, corr);
                     if (++Cc.k == Cc.nk) {
                         epilogue(lead, corr, Cc.C, Cc.ldc, c_is_f64, Cc.M, Cc.N, Cc.m0, Cc.n0);
 #pragma unroll
@@ -1064,10 +1106,11 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
 // global-to-LDS ring of b buffers (SplitTileDirect, BK = 32); S = 20: fused
 // split (SplitTileFused, BK = 32, FP32 operands, no plane pass); S = 20 + r
 // (r = 1..4): the fused split with buffer loads and r K steps in flight in
-// registers (SplitTileFusedRing).
+// registers (SplitTileFusedRing); S = 30 + r: the same with paired 128-byte
+// LDS lines.
 // IL asks the direct tile of the 2-plane method for interleaved planes.
 template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool IL = false,
-          int KIND = (S > 20 ? 3 : S == 20 ? 2 : S >= 10 ? 1 : 0)>
+          int KIND = (S > 30 ? 4 : S > 20 ? 3 : S == 20 ? 2 : S >= 10 ? 1 : 0)>
 struct SplitTileSel {
     typedef SplitTile<NPROD, BM, BN, BK, WM, WN, S> type;
 };
@@ -1084,6 +1127,11 @@ template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool IL>
 struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, IL, 3> {
     static_assert(BK == 32, "the fused tile steps K by 32");
     typedef SplitTileFusedRing<NPROD, BM, BN, WM, WN, S - 20> type;
+};
+template <int NPROD, int BM, int BN, int BK, int WM, int WN, int S, bool IL>
+struct SplitTileSel<NPROD, BM, BN, BK, WM, WN, S, IL, 4> {
+    static_assert(BK == 32, "the fused tile steps K by 32");
+    typedef SplitTileFusedRing<NPROD, BM, BN, WM, WN, S - 30, true> type;
 };
 
 }  // namespace mm

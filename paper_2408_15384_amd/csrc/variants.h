@@ -45,7 +45,9 @@
 // loads (BK 32) -- all three read bfloat16 planes made by a split pass -- or
 // 20: the fused tile, which reads the FP32 operands and splits them on the
 // way into LDS (BK 32, no plane pass, no workspace); 20 + r: the fused tile
-// with buffer loads and r K steps in flight in registers.  A direct ring deeper
+// with buffer loads and r K steps in flight in registers (64-byte LDS rows);
+// 30 + r: the same with paired 128-byte LDS lines (one K step in flight
+// measured fastest: deeper register rings cost occupancy).  A direct ring deeper
 // than LDS holds for the method's planes is made shallower (variant 14 is a
 // 3-buffer ring with 2 planes, a 2-buffer one with 3).
 #define MM_SPLIT_VARIANTS(X)          \
@@ -64,10 +66,7 @@
     X(12, 128, 128, 32, 64, 32, 20)   \
     X(13, 128, 128, 32, 64, 64, 20)   \
     X(14, 256, 128, 32, 64, 64, 13)   \
-    X(15, 64, 64, 32, 32, 32, 22)     \
-    X(16, 64, 64, 32, 32, 32, 23)     \
-    X(17, 128, 64, 32, 64, 32, 22)    \
-    X(18, 128, 64, 32, 64, 32, 23)    \
-    X(19, 128, 128, 32, 64, 64, 22)   \
-    X(20, 64, 64, 32, 32, 32, 21)     \
-    X(21, 128, 64, 32, 64, 32, 21)
+    X(15, 64, 64, 32, 32, 32, 31)     \
+    X(16, 128, 64, 32, 64, 32, 31)    \
+    X(17, 64, 64, 32, 32, 32, 21)     \
+    X(18, 128, 64, 32, 64, 32, 21)
