@@ -173,7 +173,7 @@ __global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 && TG::LDS_ELEMS * sizeof(
 }
 
 template <typename ST, bool PERSISTENT>
-__global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void grouped_split_gemm_kernel(
+__global__ __launch_bounds__(ST::NT, PERSISTENT ? (ST::NWAVES >= 8 ? 2 : 1) : SplitWaves<ST>::value) void grouped_split_gemm_kernel(
     const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter, const TileRef *) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
     if constexpr (PERSISTENT) {
@@ -235,19 +235,8 @@ struct TicketSeq {
     }
 };
 
-// Waves per SIMD the streamed kernel is compiled for: as many 4-wave
-// workgroups as the CU's LDS holds (the one-workgroup-per-tile kernel reaches
-// that occupancy by itself; the stream's extra state must not lower it).
 template <typename ST>
-constexpr int stream_waves() {
-    constexpr int lds = ST::LDS_ELEMS * 2 + 64;
-    constexpr int wgs = (160 * 1024) / lds;
-    constexpr int w = wgs * ST::NWAVES / 4;
-    return w < 1 ? 1 : (w > 4 ? 4 : w);
-}
-
-template <typename ST>
-__global__ __launch_bounds__(ST::NT, stream_waves<ST>()) void grouped_split_stream_kernel(const GroupedDesc *__restrict__ descs,
+__global__ __launch_bounds__(ST::NT, ST::WAVES) void grouped_split_stream_kernel(const GroupedDesc *__restrict__ descs,
                                                                           int count, int64_t total_tiles,
                                                                           int *counter,
                                                                           const TileRef *__restrict__ tiles) {

@@ -181,7 +181,7 @@ __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void split_gemm_
 }
 
 template <typename ST>
-__global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void split_fused_kernel(
+__global__ __launch_bounds__(ST::NT, SplitWaves<ST>::value) void split_fused_kernel(
     const float *__restrict__ A, int64_t lda, const float *__restrict__ B, int64_t ldb, void *C, int64_t ldc,
     int c_is_f64, int64_t M, int64_t N, int64_t K, int64_t tiles_m, int64_t tiles_n) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];

@@ -13,6 +13,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 #include "gptr.h"
 
@@ -717,6 +718,20 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
     using Base::NP; using Base::NWN; using Base::NWAVES; using Base::NT; using Base::FM; using Base::FN;
     using Base::LD; using Base::A_PLANE; using Base::B_PLANE; using Base::STAGE; using Base::LDS_ELEMS;
     static constexpr int RS = RS_;
+    // Waves per SIMD the kernels around this tile are compiled for: as many
+    // workgroups as the CU's LDS holds (160 KiB, less 64 bytes of kernel
+    // state), so the register budget never lowers the occupancy LDS allows.
+    static constexpr int WAVES = [] {
+        const int wgs = (160 * 1024) / (LDS_ELEMS * 2 + 64);
+        const int w = wgs * NWAVES / 4;
+        return w < 1 ? 1 : (w > 4 ? 4 : w);
+    }();
+    // Products and the next step's split in one block (see step()), so that
+    // the scheduler may overlap the split's vector work with the matrix
+    // instructions: measured slower (the longer live ranges cost registers:
+    // grouped split6 0.32 -> 0.34 ms, 8192 split6 170 -> 160 TFLOP/s), so
+    // products and split stay in sequence.
+    static constexpr bool INTERLEAVE = false;
     // PAIRED: rows r and r + 8 of each 16-row group share one 128-byte LDS
     // line (chunk ^ (row/2 mod 4)), so the 16 rows of a fragment read cover
     // all banks once; otherwise SplitTile's 64-byte rows.
@@ -883,6 +898,31 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
         }
     }
 
+    // The products of the K step in `cur` and the put of the next step (held
+    // in Rn, `kn` valid K entries; negative: there is none) into `nxt`.  Each
+    // case is one straight block of products and split, so the scheduler can
+    // interleave the split's vector work with the matrix instructions.
+    static __device__ __forceinline__ void step(const uint16_t *cur, uint16_t *nxt, const Regs &Rn, int64_t kn,
+                                                f32x4 (&lead)[FM][FN], f32x4 (&corr)[FM][FN]) {
+        if constexpr (!INTERLEAVE) {
+            compute(cur, cur + NP * A_PLANE, lead, corr);
+            if (kn >= 0) put(nxt, Rn, kn);
+            return;
+        }
+        if (kn >= BK) {
+            compute(cur, cur + NP * A_PLANE, lead, corr);
+            put_mode<0>(nxt, Rn, BK);
+        } else if (kn > 0) {
+            compute(cur, cur + NP * A_PLANE, lead, corr);
+            put_mode<1>(nxt, Rn, (int)kn);
+        } else if (kn == 0) {
+            compute(cur, cur + NP * A_PLANE, lead, corr);
+            put_mode<2>(nxt, Rn, 0);
+        } else {
+            compute(cur, cur + NP * A_PLANE, lead, corr);
+        }
+    }
+
     // `kvalid`: valid K entries of the step (at least BK for a whole step).
     // Each case is a complete put of its own, so the common whole-step path
     // carries no masking work and no register copies from a join.
@@ -952,9 +992,8 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
                     if (kt < nkt) {
                         // slot r held step kt (already in LDS): refill it with kt + RS
                         if (kt + RS < nkt) load(R[r], o, Ap, lda, Bp, ldb, rows_left, cols_left, K, kt + RS);
-                        const uint16_t *cur = smem + (kt & 1) * STAGE;
-                        compute(cur, cur + NP * A_PLANE, lead, corr);
-                        if (kt + 1 < nkt) put(smem + ((kt + 1) & 1) * STAGE, R[(r + 1) % RS], K - (kt + 1) * BK);
+                        step(smem + (kt & 1) * STAGE, smem + ((kt + 1) & 1) * STAGE, R[(r + 1) % RS],
+                             kt + 1 < nkt ? K - (kt + 1) * BK : -1, lead, corr);
                         __syncthreads();
                     }
                 }
@@ -1021,7 +1060,10 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
     template <typename Seq, typename Decode>
     static __device__ __forceinline__ void next_load(LoadCursor &L, Regs &R, int64_t &kvalid, int64_t total, Seq &seq,
                                                      Decode &decode) {
-        if (L.t >= total) return;
+        if (L.t >= total) {
+            kvalid = -1;   // past the end of the stream: nothing to put
+            return;
+        }
         if (L.K > 0) {
             load(R, L.o, L.Ap, L.lda, L.Bp, L.ldb, L.rows_left, L.cols_left, L.K, L.k);
             kvalid = L.K - L.k * BK;
@@ -1069,7 +1111,7 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
         int64_t kv[RS];
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
-            kv[r] = 0;
+            kv[r] = -1;
             next_load(L, R[r], kv[r], total, seq, decode);
         }
         put(smem, R[0], kv[0]);
@@ -1081,8 +1123,9 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
                 if (live) {
                     // stream step g + r is in LDS buffer (g + r) & 1; slot r is free
                     next_load(L, R[r], kv[r], total, seq, decode);
-                    const uint16_t *cur = smem + ((g + r) & 1) * STAGE;
-                    compute(cur, cur + NP * A_PLANE, lead, corr);
+                    // products of this step, split of the next stream step (if any)
+                    step(smem + ((g + r) & 1) * STAGE, smem + ((g + r + 1) & 1) * STAGE, R[(r + 1) % RS],
+                         kv[(r + 1) % RS], lead, corr);
                     if (++Cc.k == Cc.nk) {
                         epilogue(lead, corr, Cc.C, Cc.ldc, c_is_f64, Cc.M, Cc.N, Cc.m0, Cc.n0);
 #pragma unroll
@@ -1094,12 +1137,20 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
                             }
                         live = open_compute(Cc, Cc.i + 1, total, seq, decode);
                     }
-                    if (live) put(smem + ((g + r + 1) & 1) * STAGE, R[(r + 1) % RS], kv[(r + 1) % RS]);
                     __syncthreads();
                 }
             }
         }
     }
+};
+
+// Waves per SIMD for a kernel around split tile ST: the ring tiles ask for
+// the LDS-limited occupancy, the others for 2 (8-wave tiles) or 1.
+template <typename ST, typename = void> struct SplitWaves {
+    static constexpr int value = ST::NWAVES >= 8 ? 2 : 1;
+};
+template <typename ST> struct SplitWaves<ST, std::void_t<decltype(ST::RS)>> {
+    static constexpr int value = ST::WAVES;
 };
 
 // Variant selector: S = 1, 2 register stages (SplitTile); S = 10 + b: direct
