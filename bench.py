@@ -317,7 +317,14 @@ class ServingWorkload:
         return out
 
 
-def serving_section(torch, mm, wl=None, slots=8, max_batch=64, budget=64 << 30, variants=None, check=16):
+def serving_section(torch, mm, wl=None, slots=8, max_batch=64, budget=64 << 30, variants=None, check=16,
+                    rate=None, probe=True):
+    """One serving run of the workload's request stream.  `rate` replays the
+    same requests with their arrival times scaled to that rate (default: the
+    workload's own).  `check` requests are checked against the oracle: a
+    seeded sample of the smaller ones entry by entry, plus the largest
+    binary64 and the largest split request of the large class (M*N >= 1024^2)
+    on seeded rows, all columns."""
     import oracle
     if wl is None:
         wl = ServingWorkload(torch, mm)
@@ -325,6 +332,8 @@ def serving_section(torch, mm, wl=None, slots=8, max_batch=64, budget=64 << 30, 
         variants = wl.tune(mm)
     small_v, large_v = variants
     count = wl.count
+    rate = float(rate or wl.rate)
+    t_arr = wl.t_arr * (wl.rate / rate)
     kw = dict(budget_bytes=budget, slots=slots, max_batch=max_batch, variants=small_v, variants_large=large_v,
               large_mn=wl.LARGE_MN)
     srv = mm.Server(**kw)
@@ -337,7 +346,7 @@ def serving_section(torch, mm, wl=None, slots=8, max_batch=64, budget=64 << 30, 
         start = srv.clock() + 0.05
         ids = []
         for i, (prob, method, *_) in enumerate(wl.reqs):
-            due = start + float(wl.t_arr[i])
+            due = start + float(t_arr[i])
             while srv.clock() < due:
                 pass
             ids.append(srv.submit_raw(prob, method, due))
@@ -349,52 +358,85 @@ def serving_section(torch, mm, wl=None, slots=8, max_batch=64, budget=64 << 30, 
     finally:
         srv.close()
     torch.cuda.synchronize()
-    # oracle check of a sample of the smaller requests
-    small = [i for i in range(count) if float(wl.dims[i][0]) * wl.dims[i][1] * wl.dims[i][2] <= 1e8]
-    sample = np.random.default_rng(3).choice(small, size=min(check, len(small)), replace=False) if check else []
+    # oracle check: a sample of the smaller requests (every entry) and the
+    # largest request of each method in the large class (seeded rows)
+    flops = np.array([float(d[0]) * d[1] * d[2] for d in wl.dims])
+    small = [i for i in range(count) if flops[i] <= 1e8]
+    sample = list(np.random.default_rng(3).choice(small, size=min(check, len(small)), replace=False)) if check else []
+    large_checked = []
+    if check:
+        for is64 in (True, False):
+            idx = [i for i in range(count) if bool(wl.is_f64[i]) == is64 and
+                   int(wl.dims[i][0]) * int(wl.dims[i][1]) >= wl.LARGE_MN]
+            if idx:
+                large_checked.append(int(max(idx, key=lambda i: flops[i])))
     worst = 0.0
-    for i in sample:
+    checked = []
+    for i in [*sample, *large_checked]:
         prob, method, (ra, ca, rb, cb), C = wl.reqs[i][:4]
         M, N, K = prob.M, prob.N, prob.K
         bank = wl.bank64 if method == mm.MM_F64 else wl.bank32
-        A = bank[0][ra:ra + M, ca:ca + K]
+        rows = np.arange(M) if i in sample else np.unique(np.random.default_rng(int(i)).integers(0, M, 6))
+        A = bank[0][ra:ra + M, ca:ca + K][rows]
         B = bank[1][rb:rb + K, cb:cb + N]
-        got = C.cpu().numpy().astype(np.float64)
+        got = C.cpu().numpy().astype(np.float64)[rows]
         if method == mm.MM_F64:
             R = oracle.gemm(A, B)
             bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F64)
         else:
             R = oracle.split_product(A, B, 6)
             bound = oracle.elementwise_bound(oracle.abs_product(A, B), K, oracle.U_F32) + 2.0 ** -24 * np.abs(R)
-        worst = max(worst, float((np.abs(got - R) / np.maximum(bound, 1e-300)).max()))
+        ratio = float((np.abs(got - R) / np.maximum(bound, 1e-300)).max())
+        worst = max(worst, ratio)
+        checked.append({"request": int(i), "method": "f64" if method == mm.MM_F64 else "split6", "M": M, "N": N,
+                        "K": K, "rows": "all" if i in sample else [int(r) for r in rows],
+                        "max_err_over_bound": ratio})
     # binary64 residual probe (Freivalds) of every served result, on the GPU
-    res2 = torch.empty((count, 2), dtype=torch.float64, device="cuda")
-    x_all = torch.from_numpy(I.probe_vector(4096)).cuda()
-    rws = torch.empty(mm.lib().mm_residual_workspace_bytes(4096, 4096, 4096), dtype=torch.uint8, device="cuda")
-    for i, (prob, method, _, C, A, B) in enumerate(wl.reqs):
-        mm.residual_f64(A, B, C, x_all[:prob.N], out=res2[i], workspace=rws)
-    r2z2 = res2.cpu().numpy()
-    rel = np.sqrt(r2z2[:, 0] / np.maximum(r2z2[:, 1], 1e-300))
-    f64_mask = np.array([m == mm.MM_F64 for _, m, *_ in wl.reqs])
-    freivalds = {k: {"requests": int(msk.sum()), "median": float(np.median(rel[msk])), "max": float(rel[msk].max())}
-                 for k, msk in (("f64", f64_mask), ("split6", ~f64_mask)) if msk.any()}
-    del res2, rws
+    freivalds = None
+    if probe:
+        res2 = torch.empty((count, 2), dtype=torch.float64, device="cuda")
+        x_all = torch.from_numpy(I.probe_vector(4096)).cuda()
+        rws = torch.empty(mm.lib().mm_residual_workspace_bytes(4096, 4096, 4096), dtype=torch.uint8, device="cuda")
+        for i, (prob, method, _, C, A, B) in enumerate(wl.reqs):
+            mm.residual_f64(A, B, C, x_all[:prob.N], out=res2[i], workspace=rws)
+        r2z2 = res2.cpu().numpy()
+        rel = np.sqrt(r2z2[:, 0] / np.maximum(r2z2[:, 1], 1e-300))
+        f64_mask = np.array([m == mm.MM_F64 for _, m, *_ in wl.reqs])
+        freivalds = {k: {"requests": int(msk.sum()), "median": float(np.median(rel[msk])), "max": float(rel[msk].max())}
+                     for k, msk in (("f64", f64_mask), ("split6", ~f64_mask)) if msk.any()}
+        del res2, rws
     flop = float(sum(2.0 * d[0] * d[1] * d[2] for d in wl.dims))
-    span = float(wl.t_arr[-1])
+    span = float(t_arr[-1])
     mix_roof_s = sum(2.0 * d[0] * d[1] * d[2] / (PEAK["f64"] * 1e12) if f else
                      6 * 2.0 * d[0] * d[1] * d[2] / (PEAK["bf16"] * 1e12) for d, f in zip(wl.dims, wl.is_f64))
-    res = {"requests": count, "rate_per_s": wl.rate, "budget_bytes": budget, "slots": slots,
+    res = {"requests": count, "rate_per_s": rate, "budget_bytes": budget, "slots": slots,
            "max_batch": max_batch, "large_mn": wl.LARGE_MN,
            "variants": {"f64": [small_v[0], large_v[0]], "split6": [small_v[3], large_v[3]]}, "failed": int(bad),
            "p50_ms": stats["p50_ms"], "p99_ms": stats["p99_ms"], "mean_ms": stats["mean_ms"],
            "max_ms": stats["max_ms"], "tflops": stats["tflops"], "useful_flop": flop,
            "offered_load_rho": mix_roof_s / span, "peak_bytes_in_flight": stats["peak_bytes"],
            "launches": stats["launches"], "mean_batch": stats["mean_batch"],
-           "oracle_checked": len(sample), "oracle_max_err_over_bound": worst,
-           "freivalds_rel_residual_all": freivalds}
-    log(f"  serving slots={slots} batch={max_batch} v={variants}: p50 {res['p50_ms']:.3f} ms "
-        f"p99 {res['p99_ms']:.3f} ms {res['tflops']:.1f} TFLOP/s, {res['launches']} launches")
+           "oracle_checked": len(checked), "oracle_max_err_over_bound": worst, "oracle_checks": checked,
+           "freivalds_rel_residual_all": freivalds,
+           "served_load_rho": stats["tflops"] * 1e12 * mix_roof_s / flop if flop else None}
+    log(f"  serving {rate:.0f}/s budget {budget / 2**30:.2f} GiB slots={slots} batch={max_batch} v={variants}: "
+        f"p50 {res['p50_ms']:.3f} ms p99 {res['p99_ms']:.3f} ms {res['tflops']:.1f} TFLOP/s, "
+        f"rho {res['offered_load_rho']:.2f}, peak {res['peak_bytes_in_flight'] / 2**30:.2f} GiB, "
+        f"{res['launches']} launches")
     return res
+
+
+def serving_load_section(torch, mm, wl, variants):
+    """The same 10,000 requests at higher arrival rates (offered load rho up to
+    ~0.8 of the peak-rate mix roofline) and at the default rate under a budget
+    small enough that admission binds: p50/p99, throughput and peak bytes."""
+    points = []
+    for rate, budget in ((40000.0, 64 << 30), (60000.0, 64 << 30), (20000.0, 1 << 30)):
+        r = serving_section(torch, mm, wl=wl, variants=variants, budget=budget, check=0, rate=rate, probe=False)
+        points.append({k: r[k] for k in ("rate_per_s", "budget_bytes", "offered_load_rho", "served_load_rho", "p50_ms", "p99_ms",
+                                         "mean_ms", "max_ms", "tflops", "peak_bytes_in_flight", "launches",
+                                         "mean_batch", "failed")})
+    return points
 
 
 def strassen_section(torch, mm, n=8192, reps=5):
@@ -662,7 +704,12 @@ def main():
         torch.cuda.empty_cache()
     if "serving" in sections:
         log("serving: 10,000 requests")
-        line["serving"] = serving_section(torch, mm)
+        wl = ServingWorkload(torch, mm)
+        variants = wl.tune(mm)
+        line["serving"] = serving_section(torch, mm, wl=wl, variants=variants)
+        line["serving"]["load_points"] = serving_load_section(torch, mm, wl, variants)
+        del wl
+        torch.cuda.empty_cache()
     if "strassen" in sections:
         log("strassen: one Strassen-Winograd level at N=8192")
         line["strassen"] = strassen_section(torch, mm)
