@@ -95,16 +95,63 @@ def test_grouped_more_problems_than_the_staged_table(mm, method):
     equals the single-problem kernel (a 64x64 variant for the split form)."""
     shapes = ragged_shapes(1100, 1, 48, seed=31)
     As, Bs, Cs, hostAB = make_batch(method, shapes, seed=32)
-    variant = 1 if method == "f32" else 8
-    ref = singles(mm, method, variant, As, Bs)
-    for schedule in (0, 1, 2, 3):
-        for C in Cs:
-            C.fill_(float("nan"))
-        mm.gemm_grouped(method, As, Bs, Cs, variant=variant, schedule=schedule)
-        torch.cuda.synchronize()
-        for i, C in enumerate(Cs):
-            assert np.array_equal(C.cpu().numpy(), ref[i]), f"schedule {schedule} problem {i}"
+    # split: a plane-reading variant and a ring-fused one (streamed form)
+    for variant in ([1] if method == "f32" else [8, ring_variants(mm, method)[0]]):
+        ref = singles(mm, method, variant, As, Bs)
+        for schedule in (0, 1, 2, 3):
+            for C in Cs:
+                C.fill_(float("nan"))
+            mm.gemm_grouped(method, As, Bs, Cs, variant=variant, schedule=schedule)
+            torch.cuda.synchronize()
+            for i, C in enumerate(Cs):
+                assert np.array_equal(C.cpu().numpy(), ref[i]), f"variant {variant} schedule {schedule} problem {i}"
     check_oracle(method, hostAB, Cs, range(0, len(shapes), 50))
+
+
+def ring_variants(mm, method):
+    """The ring-fused split variants (buffer loads, pairwise planes): those with a
+    streamed persistent form."""
+    return [v for v in range(mm.variant_count(method)) if mm.variant_info(method, v)[2] == 32 and v >= 15]
+
+
+@pytest.mark.parametrize("method", ["split3", "split6"])
+def test_grouped_streamed_every_schedule(mm, method):
+    """Ring-fused variants under every schedule (0 and 1: the streamed
+    persistent form with a fixed stride; 2: with per-XCD tickets; 3: one
+    workgroup per tile), on a ragged batch with a K == 0 problem, an empty one
+    and a 1x1x1 one: each equals the single-problem kernel bit for bit.  Then
+    a batch with one problem whose leading dimension is too large for the
+    ring's 31-bit lane offsets, which runs the plain persistent form."""
+    shapes = ragged_shapes(40, 1, 300, seed=41)
+    As, Bs, Cs, hostAB = make_batch(method, shapes, seed=42)
+    for variant in ring_variants(mm, method):
+        ref = singles(mm, method, variant, As, Bs)
+        for schedule in (0, 1, 2, 3):
+            for C in Cs:
+                C.fill_(float("nan"))
+            mm.gemm_grouped(method, As, Bs, Cs, variant=variant, schedule=schedule)
+            torch.cuda.synchronize()
+            for i, C in enumerate(Cs):
+                assert np.array_equal(C.cpu().numpy(), ref[i]), f"variant {variant} schedule {schedule} problem {i}"
+    check_oracle(method, hostAB, Cs, range(len(shapes)))
+    # one operand view with lda = 2^23 + 2^18 floats (two rows of a 35 MB
+    # buffer): 63 rows of it span more than 2^31 bytes
+    lda = (1 << 23) + (1 << 18)
+    big = torch.zeros(lda + 40, dtype=torch.float32, device="cuda")
+    A0 = torch.as_strided(big, (2, 40), (lda, 1))
+    A0.copy_(torch.from_numpy(I.pair("uniform_f32", 2, 30, 40, seed=43)[0]).cuda())
+    B0 = torch.from_numpy(I.pair("uniform_f32", 2, 30, 40, seed=43)[1]).cuda()
+    As2, Bs2 = [A0, *As[:6]], [B0, *Bs[:6]]
+    Cs2 = [torch.full((a.shape[0], b.shape[1]), float("nan"), dtype=torch.float32, device="cuda") for a, b in zip(As2, Bs2)]
+    variant = ring_variants(mm, method)[0]
+    ref = singles(mm, method, variant, As2, Bs2)
+    for schedule in (1, 2):
+        for C in Cs2:
+            C.fill_(float("nan"))
+        mm.gemm_grouped(method, As2, Bs2, Cs2, variant=variant, schedule=schedule)
+        torch.cuda.synchronize()
+        for i, C in enumerate(Cs2):
+            assert np.array_equal(C.cpu().numpy(), ref[i]), f"large lda, schedule {schedule} problem {i}"
 
 
 @pytest.mark.parametrize("method", ["split3", "split6"])
