@@ -264,7 +264,9 @@ def grouped_section(torch, mm, reps=10):
 class ServingWorkload:
     """Request stream of the serving configuration with resident operands: every
     request's A and B are views into seeded 4096 x 4096 operand banks (binary64
-    for FP64 requests, FP32 for split ones) at seeded offsets; C is per request."""
+    for FP64 requests, FP32 for split ones) at seeded offsets (columns in whole
+    32-byte units, so each view starts aligned like an allocation of its own);
+    C is per request."""
 
     def __init__(self, torch, mm, count=10000, rate=20000.0, seed=0):
         self.count, self.rate = count, rate
@@ -283,8 +285,10 @@ class ServingWorkload:
         p64 = p32 = 0
         for i in range(count):
             M, N, K = (int(v) for v in self.dims[i])
-            ra, ca = offs[i, 0] % (4097 - M), offs[i, 1] % (4097 - K)
-            rb, cb = offs[i, 2] % (4097 - K), offs[i, 3] % (4097 - N)
+            # column offsets in whole 32-byte units: each request's operands
+            # start aligned, as separate allocations would
+            ra, ca = offs[i, 0] % (4097 - M), (offs[i, 1] % (4097 - K)) // 4 * 4
+            rb, cb = offs[i, 2] % (4097 - K), (offs[i, 3] % (4097 - N)) // 4 * 4
             if self.is_f64[i]:
                 A, B = self.d64[0][ra:ra + M, ca:ca + K], self.d64[1][rb:rb + K, cb:cb + N]
                 C = self.out64[p64:p64 + M * N].view(M, N)

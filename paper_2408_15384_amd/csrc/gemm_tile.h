@@ -270,10 +270,13 @@ struct TileGemm {
 // ds_read2_b64), but per K step the LDS is busy ~900 cycles against 8,192
 // MFMA cycles per SIMD, so it does not bound the tile.  Rows of A past M and
 // column chunks of B past N are clamped in bounds (they only feed entries of
-// C that are not stored).  It needs K % BK == 0, N, lda, ldb multiples of the
-// 16-byte vector, 16-byte aligned bases and K slices whose lane offsets fit
-// 31 bits; other problems run the register-staged tile (same tile shape) in
-// the same kernel.
+// C that are not stored).  Any K: a last step past K reads through byte
+// ranges that end at the operands' last valid elements and clears A's columns
+// past K in LDS (clear_a_tail); column chunks of B reaching past N feed only
+// entries of C that are not stored.  It needs lda and ldb multiples of the
+// 16-byte vector, N at least one vector, 16-byte aligned bases and K slices
+// whose lane offsets fit 31 bits; other problems run the register-staged tile
+// (same tile shape) in the same kernel.
 typedef __attribute__((address_space(3))) void mm_lvoid;
 
 template <typename T, int BM_, int BN_, int BK_, int WM_, int WN_, int STAGES_>
@@ -330,7 +333,10 @@ struct TileGemmDirect {
                 const int row = Q / B_CPR;
                 const int c = swz_b(row, Q % B_CPR);
                 int64_t gc = n0 + c * VEC;
-                gc = gc < N ? gc : N - VEC;
+                // chunks past N re-read the last chunk holding valid columns
+                // (vector-aligned, so every load stays 16-byte aligned)
+                const int64_t last = (N - 1) / VEC * VEC;
+                gc = gc < N ? gc : last;
                 voff[j] = (uint32_t)((row * ldb + (gc - n0)) * (int64_t)sizeof(T));
             }
         }
@@ -342,9 +348,9 @@ struct TileGemmDirect {
     // a flat access and then waits for every outstanding LDS read at each
     // fragment use; with buffer loads its waits stay per sub-step.)
     static __device__ __forceinline__ void issue(const T *A_slice, const T *B_slice, const uint32_t (&voff)[LOADS],
-                                                 T *buf) {
+                                                 T *buf, int32_t a_bytes = 0x7fffffff, int32_t b_bytes = 0x7fffffff) {
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-        const __amdgpu_buffer_rsrc_t ra = rsrc(A_slice), rb = rsrc(B_slice);
+        const __amdgpu_buffer_rsrc_t ra = rsrc(A_slice, a_bytes), rb = rsrc(B_slice, b_bytes);
 #pragma unroll
         for (int j = 0; j < LOADS; ++j) {
             // wave-uniform (A_SLOTS % 64 == 0); per load when A fills whole loads
@@ -354,9 +360,32 @@ struct TileGemmDirect {
         }
     }
 
-    static __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const T *base) {
-        // raw buffer (stride 0), byte range 2^31 - 1, gfx9 default format word
-        return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, 0x7fffffff, 0x00020000);
+    static __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const T *base, int32_t bytes = 0x7fffffff) {
+        // raw buffer (stride 0), byte range `bytes` (loads past it read zero),
+        // gfx9 default format word
+        return __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, bytes, 0x00020000);
+    }
+
+    // The last K step of a K that is not a multiple of BK (`krem` valid
+    // entries): the ring loads of that step run with byte ranges ending at the
+    // last valid element of each operand, so rows of B past K -- and the
+    // chunks of A's last row past K -- read as zero; A's other rows bring the
+    // next row's leading elements (or padding) past K, which each lane clears
+    // in the LDS slots it filled itself, after its loads have landed and
+    // before the barrier that publishes the step.
+    static __device__ __forceinline__ void clear_a_tail(T *buf, int krem) {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int j = 0; j < LOADS; ++j) {
+            const int P = (j * NWAVES + wave) * 64 + lane;
+            if (P < A_SLOTS) {
+                const int c = swz_a(P / A_CPR, P % A_CPR);
+#pragma unroll
+                for (int e = 0; e < VEC; ++e)
+                    if (c * VEC + e >= krem) buf[P * VEC + e] = T(0);
+            }
+        }
     }
 
     // Fragments of one stage, read one MFMA sub-step ahead of the MFMAs that
@@ -429,8 +458,52 @@ struct TileGemmDirect {
         // the per-lane offsets within a slice must fit the buffer range
         const int64_t a_span = ((int64_t)(BM - 1) * lda + BK) * (int64_t)sizeof(T);
         const int64_t b_span = ((int64_t)(BK - 1) * ldb + BN) * (int64_t)sizeof(T);
-        return K % BK == 0 && N % VEC == 0 && N >= VEC && lda % VEC == 0 && ldb % VEC == 0 &&
+        (void)K;
+        return N >= VEC && lda % VEC == 0 && ldb % VEC == 0 &&
                ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && a_span < 0x7fffffff && b_span < 0x7fffffff;
+    }
+
+    // The K loop over the ring.  RAGGED (K not a multiple of BK, or N not a
+    // multiple of the vector): the last step's loads run through byte ranges
+    // ending at the operands' last valid elements -- so no load reaches past
+    // B's last row, which may end before the vector that holds column N-1
+    // does -- and A's columns past K are cleared (clear_a_tail).
+    template <bool RAGGED>
+    static __device__ __forceinline__ void ring(const T *A_tile, int64_t lda, const T *B_tile, int64_t ldb, int64_t M,
+                                                int64_t N, int64_t K, int64_t m0, int64_t n0,
+                                                const uint32_t (&voff)[LOADS], acc_t (&acc)[FM][FN], T *smem) {
+        const int64_t nkt = (K + BK - 1) / BK;
+        const int krem = (int)(K - (nkt - 1) * BK);   // valid entries of the last step, 1..BK
+        // byte ranges of the last step, from its slices' bases (every lane
+        // offset is below 2^31, so a longer range is capped there)
+        auto cap = [](int64_t bytes) { return (int32_t)(bytes < 0x7fffffff ? bytes : 0x7fffffff); };
+        const int32_t a_last = RAGGED ? cap(((M - 1 - m0) * lda + krem) * (int64_t)sizeof(T)) : 0x7fffffff;
+        const int32_t b_last = RAGGED ? cap(((int64_t)(krem - 1) * ldb + (N - n0)) * (int64_t)sizeof(T)) : 0x7fffffff;
+        auto stage = [&](int64_t s_) {
+            if (RAGGED && s_ == nkt - 1)
+                issue(A_tile + s_ * BK, B_tile + s_ * BK * ldb, voff, smem + (s_ % STAGES) * STAGE_ELEMS, a_last, b_last);
+            else
+                issue(A_tile + s_ * BK, B_tile + s_ * BK * ldb, voff, smem + (s_ % STAGES) * STAGE_ELEMS);
+        };
+#pragma unroll
+        for (int s = 0; s < STAGES - 1; ++s)
+            if (s < nkt) stage(s);
+        for (int64_t kt = 0; kt < nkt; ++kt) {
+            const int64_t later = (nkt - 1 - kt) < (STAGES - 2) ? (nkt - 1 - kt) : (STAGES - 2);
+            if (later >= 2) wait_vm<2 * LOADS>();
+            else if (later == 1) wait_vm<LOADS>();
+            else wait_vm<0>();
+            if (RAGGED && kt == nkt - 1 && krem < BK) clear_a_tail(smem + (kt % STAGES) * STAGE_ELEMS, krem);
+            // stage kt is in LDS for every thread, the buffer of step kt-1 is
+            // no longer read: a bare barrier (a fenced one would also wait for
+            // the later stages' loads)
+            __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
+            __builtin_amdgcn_s_barrier();
+            compute(smem + (kt % STAGES) * STAGE_ELEMS, acc, [&] {
+                const int64_t kn = kt + STAGES - 1;
+                if (kn < nkt) stage(kn);
+            });
+        }
     }
 
     static __device__ __forceinline__ void run(const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
@@ -446,28 +519,13 @@ struct TileGemmDirect {
         for (int fm = 0; fm < FM; ++fm)
 #pragma unroll
             for (int fn = 0; fn < FN; ++fn) acc[fm][fn] = acc_t{0, 0, 0, 0};
-        const int64_t nkt = K / BK;
         uint32_t voff[LOADS];
         sources(lda, ldb, M, N, m0, n0, voff);
-        const T *A_tile = A + m0 * lda, *B_tile = B + n0;
-#pragma unroll
-        for (int s = 0; s < STAGES - 1; ++s)
-            if (s < nkt) issue(A_tile + (int64_t)s * BK, B_tile + (int64_t)s * BK * ldb, voff, smem + s * STAGE_ELEMS);
-        for (int64_t kt = 0; kt < nkt; ++kt) {
-            const int64_t later = (nkt - 1 - kt) < (STAGES - 2) ? (nkt - 1 - kt) : (STAGES - 2);
-            if (later >= 2) wait_vm<2 * LOADS>();
-            else if (later == 1) wait_vm<LOADS>();
-            else wait_vm<0>();
-            // stage kt is in LDS for every thread, the buffer of step kt-1 is
-            // no longer read: a bare barrier (a fenced one would also wait for
-            // the later stages' loads)
-            __builtin_amdgcn_s_waitcnt(15 | (7 << 4) | (0 << 8) | (3 << 14));
-            __builtin_amdgcn_s_barrier();
-            compute(smem + (kt % STAGES) * STAGE_ELEMS, acc, [&] {
-                const int64_t kn = kt + STAGES - 1;
-                if (kn < nkt) issue(A_tile + kn * BK, B_tile + kn * BK * ldb, voff, smem + (kn % STAGES) * STAGE_ELEMS);
-            });
-        }
+        // K a multiple of BK: the plain ring; otherwise the ring with a
+        // range-limited last step (two loops, so the common one carries none
+        // of the last step's bookkeeping: measured 1% on the 8192 product)
+        if (K % BK == 0 && N % VEC == 0) ring<false>(A + m0 * lda, lda, B + n0, ldb, M, N, K, m0, n0, voff, acc, smem);
+        else ring<true>(A + m0 * lda, lda, B + n0, ldb, M, N, K, m0, n0, voff, acc, smem);
         const int lane = threadIdx.x & 63;
         const int wave = threadIdx.x >> 6;
         const int wm = wave / NWN, wn = wave % NWN;

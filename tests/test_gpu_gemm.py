@@ -103,6 +103,46 @@ def test_direct_tile_shapes(mm, method, shape):
         assert np.array_equal(host(C).astype(np.float64), oracle.gemm(Ai, Bi)), f"variant {v}"
 
 
+def _padded_view(X, ld, fill=float("nan"), tight=False):
+    """X (host) as a device view with leading dimension ld in a buffer whose
+    padding holds `fill`; tight: the buffer ends at X's last element."""
+    rows, cols = X.shape
+    size = (rows - 1) * ld + cols if tight else rows * ld + 64
+    buf = torch.full((size,), fill, dtype=torch.float64 if X.dtype == np.float64 else torch.float32, device="cuda")
+    v = torch.as_strided(buf, (rows, cols), (ld, 1))
+    v.copy_(torch.from_numpy(np.ascontiguousarray(X)).cuda())
+    return v
+
+
+@pytest.mark.parametrize("method", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(257, 131, 45), (64, 5, 17), (300, 130, 1), (70, 67, 49), (33, 4, 250)])
+def test_direct_tile_any_k_and_n(mm, method, shape):
+    """The direct-to-LDS tiles on K not a multiple of their K step and N not a
+    multiple of the vector: operands are views with vector-aligned leading
+    dimensions whose padding holds NaN (A's columns past K must be cleared
+    before they meet B's zero rows), B's buffer ending at its last element (no
+    load may reach past it).  Every variant within the bound of the oracle;
+    integer inputs bit-exact."""
+    M, N, K = shape
+    elem = 8 if method == "f64" else 4
+    vec = 16 // elem
+    lda = (K + vec - 1) // vec * vec + vec
+    ldb = (N + vec - 1) // vec * vec + vec
+    u = oracle.U_F64 if method == "f64" else oracle.U_F32
+    kind = "uniform_f64" if method == "f64" else "uniform_f32"
+    for k2, (A, B) in ((kind, I.pair(kind, M, N, K, seed=M + K)),
+                       ("int", I.pair("int_f64" if method == "f64" else "int_f32", M, N, K, seed=M + K + 1))):
+        dA, dB = _padded_view(A, lda), _padded_view(B, ldb, tight=True)
+        for v in range(mm.variant_count(method)):
+            C = torch.full((M, N), float("nan"), dtype=dA.dtype, device="cuda")
+            mm.gemm_variant(method, v, dA, dB, C)
+            got = host(C).astype(np.float64)
+            if k2 == "int":
+                assert np.array_equal(got, oracle.gemm(A, B)), f"variant {v}"
+            else:
+                assert_within_bound(got, A, B, u)
+
+
 def _span_limit_ld(rows_before_last, extra, elem):
     """Largest leading dimension (a multiple of the 16-byte vector) whose
     slice span (rows_before_last * ld + extra) * elem stays below 2^31 - 1."""
