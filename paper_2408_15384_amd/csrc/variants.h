@@ -23,7 +23,8 @@
     X(11, 128, 256, 16, 64, 64, 13)   \
     X(12, 256, 128, 16, 64, 64, 12)   \
     X(13, 64, 64, 16, 32, 32, 14)     \
-    X(14, 32, 32, 16, 16, 16, 14)
+    X(14, 32, 32, 16, 16, 16, 14)     \
+    X(15, 256, 128, 16, 64, 32, 12)
 
 #define MM_F32_VARIANTS(X)            \
     X(0, 128, 128, 16, 64, 64, 0)     \
@@ -38,7 +39,8 @@
     X(9, 128, 64, 32, 64, 32, 13)     \
     X(10, 32, 32, 32, 16, 16, 0)      \
     X(11, 256, 128, 16, 64, 64, 12)   \
-    X(12, 256, 128, 32, 64, 64, 12)
+    X(12, 256, 128, 32, 64, 64, 12)   \
+    X(13, 256, 128, 32, 64, 32, 12)
 
 // Split variants carry a seventh field, S: 1 or 2 register stages of global
 // prefetch, or 10 + b: a ring of b LDS buffers fed by direct global-to-LDS
