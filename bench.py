@@ -76,11 +76,19 @@ def f64_variant_entry(variant: int) -> str:
     return m.group(0) if m else ""
 
 
+def _code_only(text: str) -> str:
+    """Source text without // comments and blank lines (a comment edit does not
+    change the compiled kernel)."""
+    import re
+    lines = (re.sub(r"//.*$", "", line).rstrip() for line in text.splitlines())
+    return "\n".join(line for line in lines if line)
+
+
 def kernel_source_hash(variant: int = 4) -> str:
     h = hashlib.sha256()
     for p in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p)) as f:
+            h.update(_code_only(f.read()).encode())
     from paper_2408_15384_amd import build as B
     h.update(repr([B.ARCH, *B.COMMON[:-2], *B.DEVICE_FLAGS]).encode())   # flags, less the include path
     h.update(f64_variant_entry(variant).encode())

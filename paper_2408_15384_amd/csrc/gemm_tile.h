@@ -264,11 +264,12 @@ struct TileGemm {
 //   B rows (BN elements) : chunk ^ (lane group of the row, shifted so the four
 //                          groups of an MFMA read sit in distinct bank ranges)
 // which spreads each 16-lane group of an A read and each lane group pair of a
-// B read over distinct banks.  The LDS counters still book about a quarter of
-// the tile's LDS cycles as conflicts (binary64 256x128: 29%, 5.6 cycles per
-// LDS instruction; the compiler merges B reads of columns 32 apart into one
-// ds_read2_b64), but per K step the LDS is busy ~900 cycles against 8,192
-// MFMA cycles per SIMD, so it does not bound the tile.  Rows of A past M and
+// B read over distinct banks.  The LDS counters still book a share of the
+// tile's LDS cycles as conflicts (binary64 256x128: 29% with 8 waves of 64x64,
+// 40% with 16 waves of 64x32, 5-5.6 cycles per LDS instruction; the compiler
+// merges B reads of columns 32 apart into one ds_read2_b64), but per K step
+// the LDS is busy ~900-1,300 cycles against 8,192 MFMA cycles per SIMD, so it
+// does not bound the tile.  Rows of A past M and
 // column chunks of B past N are clamped in bounds (they only feed entries of
 // C that are not stored).  Any K: a last step past K reads through byte
 // ranges that end at the operands' last valid elements and clears A's columns
