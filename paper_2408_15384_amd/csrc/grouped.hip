@@ -114,24 +114,35 @@ __device__ __forceinline__ void local_tile(int64_t local, int64_t tiles_m, int64
     *tn = uniform(in / gsize);
 }
 
-// One tile of a grouped launch: decode the owner's descriptor and run the
-// single-problem tile body on it.
+// Owner problem and coordinates of tile t: one load from the launch's tile
+// table when it has one, else a binary search over the descriptors' prefix
+// sums (staged in LDS when `cached`) and the in-problem order of local_tile.
+__device__ __forceinline__ void locate(const GroupedDesc *__restrict__ descs, const int32_t *s_begin, bool cached,
+                                       int count, const TileRef *__restrict__ tiles, int64_t t, int *own, int64_t *tm,
+                                       int64_t *tn) {
+    if (tiles) {
+        const TileRef r = tiles[t];
+        *own = uniform(r.own);
+        *tm = uniform(r.tm);
+        *tn = uniform(r.tn);
+        return;
+    }
+    *own = uniform(find_owner(descs, s_begin, cached, count, t));
+    const GroupedDesc &d = descs[*own];
+    local_tile(t - d.tile_begin, d.tiles_m, d.tiles_n, tm, tn);
+}
+
+// One tile of a grouped launch: run the single-problem tile body on tile
+// (tm, tn) of problem d.
 template <typename TG, typename T>
-__device__ __forceinline__ void grouped_dense_tile(const GroupedDesc *__restrict__ descs, int own, int64_t t, T *smem) {
-    const GroupedDesc &d = descs[own];
-    int64_t tm, tn;
-    local_tile(t - d.tile_begin, d.tiles_m, d.tiles_n, &tm, &tn);
+__device__ __forceinline__ void grouped_dense_tile(const GroupedDesc &d, int64_t tm, int64_t tn, T *smem) {
     const bool vec_ok = (d.lda % TG::VEC == 0) && (d.ldb % TG::VEC == 0) && ((uintptr_t)d.A % 16 == 0) &&
                         ((uintptr_t)d.B % 16 == 0);
     TG::run((const T *)d.A, d.lda, (const T *)d.B, d.ldb, (T *)d.C, d.ldc, d.M, d.N, d.K, tm, tn, vec_ok, smem);
 }
 
 template <typename ST>
-__device__ __forceinline__ void grouped_split_tile(const GroupedDesc *__restrict__ descs, int own, int64_t t,
-                                                   uint16_t *smem) {
-    const GroupedDesc &d = descs[own];
-    int64_t tm, tn;
-    local_tile(t - d.tile_begin, d.tiles_m, d.tiles_n, &tm, &tn);
+__device__ __forceinline__ void grouped_split_tile(const GroupedDesc &d, int64_t tm, int64_t tn, uint16_t *smem) {
     if constexpr (ST::FUSED) {
         // descriptors hold the FP32 operands themselves
         ST::run_fused((const float *)d.A, d.lda, (const float *)d.B, d.ldb, d.C, d.ldc, 0, d.M, d.N, d.K, tm, tn, smem);
@@ -152,45 +163,55 @@ __device__ __forceinline__ void grouped_split_tile(const GroupedDesc *__restrict
 // share a CU; otherwise one.
 template <typename TG, typename T, bool PERSISTENT>
 __global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 && TG::LDS_ELEMS * sizeof(T) <= 76 * 1024 ? 2 : 1)) void grouped_gemm_kernel(
-    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter, const TileRef *) {
+    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter,
+    const TileRef *__restrict__ tiles) {
     __shared__ __attribute__((aligned(16))) T smem[TG::LDS_ELEMS];
+    int own;
+    int64_t tm, tn;
     if constexpr (PERSISTENT) {
         __shared__ int32_t s_begin[kOwnerCap];
         __shared__ int64_t slot;
-        const bool cached = stage_begins<kOwnerCap>(descs, count, total_tiles, s_begin);
+        const bool cached = !tiles && stage_begins<kOwnerCap>(descs, count, total_tiles, s_begin);
         for (int64_t t = blockIdx.x; t < total_tiles;) {
             const int ticket = draw_ticket(counter);
-            grouped_dense_tile<TG, T>(descs, uniform(find_owner(descs, s_begin, cached, count, t)), t, smem);
+            locate(descs, s_begin, cached, count, tiles, t, &own, &tm, &tn);
+            grouped_dense_tile<TG, T>(descs[own], tm, tn, smem);
             __syncthreads();
             t = next_tile(t, counter, ticket, &slot);
         }
     } else {
         const int64_t t = chunked_tile(blockIdx.x);
-        if (t < total_tiles)
-            grouped_dense_tile<TG, T>(descs, uniform(find_owner(descs, (const int32_t *)nullptr, false, count, t)), t,
-                                      smem);
+        if (t < total_tiles) {
+            locate(descs, nullptr, false, count, tiles, t, &own, &tm, &tn);
+            grouped_dense_tile<TG, T>(descs[own], tm, tn, smem);
+        }
     }
 }
 
 template <typename ST, bool PERSISTENT>
 __global__ __launch_bounds__(ST::NT, PERSISTENT ? (ST::NWAVES >= 8 ? 2 : 1) : SplitWaves<ST>::value) void grouped_split_gemm_kernel(
-    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter, const TileRef *) {
+    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter,
+    const TileRef *__restrict__ tiles) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
+    int own;
+    int64_t tm, tn;
     if constexpr (PERSISTENT) {
         __shared__ int32_t s_begin[kOwnerCap];
         __shared__ int64_t slot;
-        const bool cached = stage_begins<kOwnerCap>(descs, count, total_tiles, s_begin);
+        const bool cached = !tiles && stage_begins<kOwnerCap>(descs, count, total_tiles, s_begin);
         for (int64_t t = blockIdx.x; t < total_tiles;) {
             const int ticket = draw_ticket(counter);
-            grouped_split_tile<ST>(descs, uniform(find_owner(descs, s_begin, cached, count, t)), t, smem);
+            locate(descs, s_begin, cached, count, tiles, t, &own, &tm, &tn);
+            grouped_split_tile<ST>(descs[own], tm, tn, smem);
             __syncthreads();
             t = next_tile(t, counter, ticket, &slot);
         }
     } else {
         const int64_t t = chunked_tile(blockIdx.x);
-        if (t < total_tiles)
-            grouped_split_tile<ST>(descs, uniform(find_owner(descs, (const int32_t *)nullptr, false, count, t)), t,
-                                   smem);
+        if (t < total_tiles) {
+            locate(descs, nullptr, false, count, tiles, t, &own, &tm, &tn);
+            grouped_split_tile<ST>(descs[own], tm, tn, smem);
+        }
     }
 }
 
@@ -572,7 +593,7 @@ struct mm_grouped_plan {
     mm::GroupedDesc *d_descs = nullptr;
     mm::SplitJob *d_jobs = nullptr;
     int *d_counter = nullptr;
-    mm::TileRef *d_tiles = nullptr;   // streamed form only
+    mm::TileRef *d_tiles = nullptr;   // tile table (owner and coordinates of every tile)
     void *ws = nullptr;
     // pinned staging ring for descriptor refreshes: each slot holds the
     // descriptors, then (at a 256-byte boundary) the split jobs
@@ -630,8 +651,9 @@ static mm_status create_plan(const mm_problem *probs, int32_t count, mm_method m
     if (e == hipSuccess && nj) e = hipMalloc(&p->d_jobs, nj * sizeof(SplitJob));
     if (e == hipSuccess && schedule == 2) e = hipMalloc(&p->d_counter, kCounters * sizeof(int));
     const int form = grouped_form(method, variant, schedule, p->layout);
-    if (e == hipSuccess && form == kFormStream && p->layout.total_tiles > 0) {
-        // the tile table depends on the shapes only: uploaded once
+    if (e == hipSuccess && p->layout.total_tiles > 0) {
+        // the tile table depends on the shapes only: uploaded once (the
+        // kernels then read each tile's owner and coordinates with one load)
         std::vector<TileRef> table;
         build_tile_table(p->layout, &table);
         e = hipMalloc(&p->d_tiles, table.size() * sizeof(TileRef));

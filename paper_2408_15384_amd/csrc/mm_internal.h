@@ -144,7 +144,8 @@ struct SplitJob {
 };
 
 // Owner problem and tile coordinates of one tile of a grouped batch (the
-// streamed form reads these instead of searching the prefix sums).
+// kernels read these, when a launch has the table, instead of searching the
+// prefix sums).
 struct TileRef {
     int32_t own, tm, tn, pad;
 };
@@ -174,11 +175,12 @@ void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_met
 // (schedules 0-2; schedule 2 draws tiles from the work counter).
 constexpr int kFormTile = 0, kFormPersistent = 1, kFormStream = 2;
 int grouped_form(mm_method method, int variant, int schedule, const Layout &L);
-// Tile table of a layout, in tile-id order (for the streamed form).
+// Tile table of a layout, in tile-id order.
 void build_tile_table(const Layout &L, std::vector<TileRef> *out);
 // Enqueue [grouped split pass] -> [counter reset] -> grouped GEMM for
 // descriptors already in device memory.
-// d_tiles: the layout's tile table on the device (streamed form only, else null).
+// d_tiles: the layout's tile table on the device; required by the streamed
+// form, optional for the others (null: they search the prefix sums).
 hipError_t grouped_enqueue(mm_method method, int variant, int form, const GroupedDesc *d_descs, int ndesc, int64_t total_tiles,
                            const SplitJob *d_jobs, int njobs, int64_t split_tiles, int *d_counter,
                            const TileRef *d_tiles, hipStream_t st);

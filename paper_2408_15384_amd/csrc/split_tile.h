@@ -726,12 +726,6 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
         const int w = wgs * NWAVES / 4;
         return w < 1 ? 1 : (w > 4 ? 4 : w);
     }();
-    // Products and the next step's split in one block (see step()), so that
-    // the scheduler may overlap the split's vector work with the matrix
-    // instructions: measured slower (the longer live ranges cost registers:
-    // grouped split6 0.32 -> 0.34 ms, 8192 split6 170 -> 160 TFLOP/s), so
-    // products and split stay in sequence.
-    static constexpr bool INTERLEAVE = false;
     // PAIRED: rows r and r + 8 of each 16-row group share one 128-byte LDS
     // line (chunk ^ (row/2 mod 4)), so the 16 rows of a fragment read cover
     // all banks once; otherwise SplitTile's 64-byte rows.
@@ -863,28 +857,16 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
         }
     }
 
-    // Split the step held in R and write its planes to LDS; `kvalid` is the
-    // number of valid K entries of the step (the A columns past it are
-    // cleared; B rows past K already read as zero).
-    // Split one K step held in R and write its planes to LDS.  MODE 0: a
-    // whole step; 1: the A columns at or past `kvalid` are cleared (the last
-    // step of a tile whose K is not a multiple of 32; B rows past K already
-    // read as zero); 2: all planes zero (the single step of a tile without K).
-    template <int MODE>
-    static __device__ __forceinline__ void put_mode(uint16_t *stage, const Regs &R, int kvalid) {
+    // Split one whole K step held in R and write its planes to LDS.
+    static __device__ __forceinline__ void put_step(uint16_t *stage, const Regs &R) {
 #pragma unroll
         for (int i = 0; i < A_UNITS; ++i) {
             const int u = threadIdx.x + i * NT;
             float x[8];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                x[e] = MODE == 2 ? 0.f : R.a[i][0][e];
-                x[4 + e] = MODE == 2 ? 0.f : R.a[i][1][e];
-            }
-            if constexpr (MODE == 1) {
-                const int c0 = (u % CHUNKS) * 8;
-#pragma unroll
-                for (int e = 0; e < 8; ++e) x[e] = c0 + e < kvalid ? x[e] : 0.f;
+                x[e] = R.a[i][0][e];
+                x[4 + e] = R.a[i][1][e];
             }
             put8(stage, A_PLANE, u / CHUNKS, u % CHUNKS, x);
         }
@@ -893,43 +875,74 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
             const int u = threadIdx.x + i * NT;
             float x[8];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) x[e] = MODE == 2 ? 0.f : R.b[i][e];
+            for (int e = 0; e < 8; ++e) x[e] = R.b[i][e];
             put8(stage + NP * A_PLANE, B_PLANE, u % BN, u / BN, x);
         }
     }
 
-    // The products of the K step in `cur` and the put of the next step (held
-    // in Rn, `kn` valid K entries; negative: there is none) into `nxt`.  Each
-    // case is one straight block of products and split, so the scheduler can
-    // interleave the split's vector work with the matrix instructions.
-    static __device__ __forceinline__ void step(const uint16_t *cur, uint16_t *nxt, const Regs &Rn, int64_t kn,
-                                                f32x4 (&lead)[FM][FN], f32x4 (&corr)[FM][FN]) {
-        if constexpr (!INTERLEAVE) {
-            compute(cur, cur + NP * A_PLANE, lead, corr);
-            if (kn >= 0) put(nxt, Rn, kn);
-            return;
+    // After put_step of a step that ends K: zero, in every plane, the A
+    // entries of this thread's units at or past column `kvalid` (B's rows
+    // past K already read as zero), and for the zero step of a tile without
+    // K (kvalid 0, nothing loaded) its B entries too.  Works on LDS only, so
+    // the whole-step path carries no masking and no extra live registers.
+    static __device__ __forceinline__ void clear_tail(uint16_t *stage, int kvalid) {
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int i = 0; i < A_UNITS; ++i) {
+            const int u = threadIdx.x + i * NT;
+            const int c0 = (u % CHUNKS) * 8;
+            if (c0 + 8 <= kvalid) continue;
+            const int off = lds_elem(u / CHUNKS, u % CHUNKS);
+#pragma unroll
+            for (int p = 0; p < NP; ++p) {
+                u32x4 *w = reinterpret_cast<u32x4 *>(stage + p * A_PLANE + off);
+                u32x4 v = {0, 0, 0, 0};
+                if (c0 < kvalid) {
+                    // the chunk K ends in: keep entries c0 + j, j < kvalid - c0
+                    v = *w;
+#pragma unroll
+                    for (int h = 0; h < 4; ++h)
+                        v[h] &= (c0 + 2 * h < kvalid ? 0x0000ffffu : 0u) | (c0 + 2 * h + 1 < kvalid ? 0xffff0000u : 0u);
+                }
+                *w = v;
+            }
         }
-        if (kn >= BK) {
-            compute(cur, cur + NP * A_PLANE, lead, corr);
-            put_mode<0>(nxt, Rn, BK);
-        } else if (kn > 0) {
-            compute(cur, cur + NP * A_PLANE, lead, corr);
-            put_mode<1>(nxt, Rn, (int)kn);
-        } else if (kn == 0) {
-            compute(cur, cur + NP * A_PLANE, lead, corr);
-            put_mode<2>(nxt, Rn, 0);
-        } else {
-            compute(cur, cur + NP * A_PLANE, lead, corr);
+        if (kvalid <= 0) {
+#pragma unroll
+            for (int i = 0; i < B_UNITS; ++i) {
+                const int u = threadIdx.x + i * NT;
+#pragma unroll
+                for (int p = 0; p < NP; ++p)
+                    *reinterpret_cast<u32x4 *>(stage + NP * A_PLANE + p * B_PLANE + lds_elem(u % BN, u / BN)) =
+                        u32x4{0, 0, 0, 0};
+            }
         }
     }
 
-    // `kvalid`: valid K entries of the step (at least BK for a whole step).
-    // Each case is a complete put of its own, so the common whole-step path
-    // carries no masking work and no register copies from a join.
+    // Split the step held in R (`kvalid` valid K entries, at least BK for a
+    // whole step) into LDS.
     static __device__ __forceinline__ void put(uint16_t *stage, const Regs &R, int64_t kvalid) {
-        if (kvalid >= BK) put_mode<0>(stage, R, BK);
-        else if (kvalid > 0) put_mode<1>(stage, R, (int)kvalid);
-        else put_mode<2>(stage, R, 0);
+        put_step(stage, R);
+        if (kvalid < BK) {
+            // Keeps this a branch of the last step: clear_tail does nothing
+            // when kvalid >= BK, and without the statement the compiler drops
+            // the test and runs clear_tail's per-lane tests on every step.
+            asm volatile("");
+            clear_tail(stage, kvalid > 0 ? (int)kvalid : 0);
+        }
+    }
+
+    // The products of the K step in `cur`, then the put of the next step
+    // (held in Rn, `kn` valid K entries; negative: there is none) into
+    // `nxt`.  Products and split stay in sequence: emitting them as one block
+    // for the scheduler to interleave measured slower (the longer live ranges
+    // cost registers: grouped split6 0.32 -> 0.34 ms, 8192 split6 170 -> 160
+    // TFLOP/s), and a wave's matrix and vector instructions do not overlap on
+    // a SIMD in any case.
+    static __device__ __forceinline__ void step(const uint16_t *cur, uint16_t *nxt, const Regs &Rn, int64_t kn,
+                                                f32x4 (&lead)[FM][FN], f32x4 (&corr)[FM][FN]) {
+        compute(cur, cur + NP * A_PLANE, lead, corr);
+        if (kn >= 0) put(nxt, Rn, kn);
     }
 
     static __device__ __forceinline__ void epilogue(const f32x4 (&lead)[FM][FN], const f32x4 (&corr)[FM][FN], void *C,

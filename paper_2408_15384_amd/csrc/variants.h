@@ -48,8 +48,9 @@
 // 20: the fused tile, which reads the FP32 operands and splits them on the
 // way into LDS (BK 32, no plane pass, no workspace); 20 + r: the fused tile
 // with buffer loads and r K steps in flight in registers (64-byte LDS rows);
-// 30 + r: the same with paired 128-byte LDS lines (one K step in flight
-// measured fastest: deeper register rings cost occupancy).  A direct ring deeper
+// 30 + r: the same with paired 128-byte LDS lines (one K step in flight:
+// two measured no faster on grouped batches and at 1024, and cost
+// occupancy where registers bound it).  A direct ring deeper
 // than LDS holds for the method's planes is made shallower (variant 14 is a
 // 3-buffer ring with 2 planes, a 2-buffer one with 3).
 #define MM_SPLIT_VARIANTS(X)          \

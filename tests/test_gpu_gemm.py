@@ -315,9 +315,10 @@ def test_split_variants_bit_identical(mm, nprod, shape):
     method = f"split{nprod}"
     A, B = I.pair("uniform_f32", M, N, K, seed=M + N)
     dA, dB = dev(A), dev(B)
-    # the same operands behind a misaligned base and padded leading dimensions
-    pa = torch.zeros((M, K + 3), dtype=torch.float32, device="cuda")
-    pb = torch.zeros((K, N + 5), dtype=torch.float32, device="cuda")
+    # the same operands behind a misaligned base and padded leading dimensions;
+    # NaN padding: a tile's last K step reads A's row past K and must clear it
+    pa = torch.full((M, K + 3), float("nan"), dtype=torch.float32, device="cuda")
+    pb = torch.full((K, N + 5), float("nan"), dtype=torch.float32, device="cuda")
     pa[:, 1:K + 1] = dA
     pb[:, 2:N + 2] = dB
     vA, vB = pa[:, 1:K + 1], pb[:, 2:N + 2]
