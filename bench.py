@@ -512,6 +512,28 @@ def peak_section(torch, achieved_f64=None):
             f"{best['chains']} chains, {best['workgroups_per_cu']} workgroups/CU")
     if achieved_f64:
         res["headline_frac_of_f64_ceiling"] = achieved_f64 / res["f64"]["tflops"]
+    # Matrix waves and vector waves on the same SIMDs: does the SIMD overlap
+    # them (both ~ the longer alone) or issue them in turn (both ~ the sum)?
+    ov = lib.mm_peak_overlap
+    ov.restype = ctypes.c_int32
+    ov.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    blocks, iters = 2 * cus, 2000
+    ovl = {}
+    for role, key in ((1, "mfma_only_ms"), (2, "valu_only_ms"), (0, "both_ms")):
+        if ov(role, blocks, 10, out_buf.data_ptr(), stream) != 0:
+            raise RuntimeError("mm_peak_overlap failed")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            if ov(role, blocks, iters, out_buf.data_ptr(), stream) != 0:
+                raise RuntimeError("mm_peak_overlap failed")
+        e1.record()
+        e1.synchronize()
+        ovl[key] = e0.elapsed_time(e1) / 3
+    ovl["both_over_sum"] = ovl["both_ms"] / (ovl["mfma_only_ms"] + ovl["valu_only_ms"])
+    res["mfma_valu_overlap"] = ovl
+    log(f"  matrix + vector waves on one SIMD: {ovl['both_ms']:.3f} ms against {ovl['mfma_only_ms']:.3f} + "
+        f"{ovl['valu_only_ms']:.3f} ms alone")
     return res
 
 
@@ -646,9 +668,9 @@ def main():
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--sections", default="peak,precision,grouped,serving,strassen,shard,layouts,paper",
+    ap.add_argument("--sections", default="peak,precision,grouped,serving,strassen,shard,layouts,paper,vendor",
                     help="comma list of sections to run after the headline (peak, precision, grouped, serving, strassen, shard, layouts, "
-                         "paper; "
+                         "paper, vendor; "
                          "or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -734,6 +756,22 @@ def main():
     if "paper" in sections:
         log("paper sizes: Box-Muller inputs, 32..1024")
         line["paper_sizes"] = paper_section(torch, mm)
+    if "vendor" in sections:
+        log("vendor: the same 8192 products in hipBLASLt / rocBLAS (torch.matmul), comparison only")
+        from paper_2408_15384_amd.workloads import vendor_rates
+        line["vendor_library"] = {"note": "torch.matmul on the same GPU, uniform inputs; context, not used by libmm",
+                                  "n": n, **vendor_rates(torch, n)}
+        vl = line["vendor_library"]
+        prec = line.get("precision", {}).get("uniform_f32", {})
+        if prec.get("fp32"):
+            vl["libmm_f32_over_vendor"] = prec["fp32"]["tflops_useful"] / vl["f32"]["tflops"]
+        # how hard each drives the bf16 matrix cores: the vendor's plain bf16
+        # product against the split products' plane products (by time)
+        vl["bf16"]["frac_of_datasheet"] = vl["bf16"]["tflops"] / PEAK["bf16"]
+        for m in ("split3", "split6"):
+            if prec.get(m):
+                vl[f"libmm_{m}_mfma_frac_over_vendor_bf16"] = prec[m]["mfma_frac"] / vl["bf16"]["frac_of_datasheet"]
+        line["vendor_library"]["libmm_f64_over_vendor"] = value / line["vendor_library"]["f64"]["tflops"]
     line["paper_context"] = {"note": "the paper's own CPU timings (Cirrus, Xeon E5-2695 2.1 GHz, 18 cores), "
                                      "context only", "serial_O3_gcc_1024_s": 1.69891,
                              "intel_16_threads_1024_s": 0.12}

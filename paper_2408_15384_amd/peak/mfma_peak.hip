@@ -76,7 +76,57 @@ void launch(int32_t dtype, int32_t blocks, int32_t iters, float *out, hipStream_
     else hipLaunchKernelGGL(peak_bf16<CH>, dim3(blocks), dim3(256), 0, st, out, iters);
 }
 
+// Waves 0-3 of each 512-thread workgroup run 8 chains of bf16 MFMAs, waves
+// 4-7 chains of FP32 fused multiply-adds; with two workgroups per CU every
+// SIMD holds matrix waves and vector waves.  ROLE 0 runs both kinds, 1 only
+// the matrix waves, 2 only the vector waves (the others exit at once).
+template <int ROLE>
+__global__ __launch_bounds__(512) void overlap_kernel(float *out, int iters) {
+    const bool matrix = (threadIdx.x >> 6) < 4;
+    float s = 0;
+    if (matrix && ROLE != 2) {
+        bf8 a, b;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            a[e] = (__bf16)(threadIdx.x * 1e-3f + e);
+            b[e] = (__bf16)(e * 0.5f);
+        }
+        f4 acc[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc[i] = f4{0, 0, 0, 0};
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i], 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s += acc[i][0] + acc[i][3];
+    }
+    if (!matrix && ROLE != 1) {
+        float x[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) x[j] = threadIdx.x * 0.01f + j;
+        for (int it = 0; it < iters; ++it) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int j = 0; j < 16; ++j) x[j] = __builtin_fmaf(x[j], 0.999f, 0.25f);
+        }
+#pragma unroll
+        for (int j = 0; j < 16; ++j) s += x[j];
+    }
+    out[blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 }  // namespace
+
+extern "C" int32_t mm_peak_overlap(int32_t role, int32_t blocks, int32_t iters, float *out, void *stream) {
+    if (blocks < 1 || iters < 1 || !out || role < 0 || role > 2) return -1;
+    hipStream_t st = (hipStream_t)stream;
+    if (role == 0) hipLaunchKernelGGL(overlap_kernel<0>, dim3(blocks), dim3(512), 0, st, out, iters);
+    else if (role == 1) hipLaunchKernelGGL(overlap_kernel<1>, dim3(blocks), dim3(512), 0, st, out, iters);
+    else hipLaunchKernelGGL(overlap_kernel<2>, dim3(blocks), dim3(512), 0, st, out, iters);
+    return hipGetLastError() == hipSuccess ? 0 : -3;
+}
 
 extern "C" int32_t mm_peak_mfma(int32_t dtype, int32_t chains, int32_t blocks, int32_t iters, float *out,
                                 void *stream) {

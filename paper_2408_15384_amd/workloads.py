@@ -3,6 +3,7 @@ output holds only their kernels.
 
     python -m paper_2408_15384_amd.workloads grouped --method split6 [--variant V --schedule S] [--reps 5]
     python -m paper_2408_15384_amd.workloads gemm --method f64 --n 8192 [--variant V] [--reps 5]
+    python -m paper_2408_15384_amd.workloads vendor --n 8192 [--reps 10]
     (--sweep V:S,V:S,... or V,V,... times several configurations in one run)
 
 grouped: the 512-problem batch (M, N, K each log-uniform on [32, 1024], seed 0,
@@ -10,7 +11,9 @@ FP32 entries uniform on [-1, 1)), one plan captured with the given tile variant
 and schedule (default: the library's choice for the batch), replayed `reps`
 times.  gemm: one square product of size n (binary64 or FP32 inputs by method,
 uniform on [-1, 1), seed 0), launched `reps` times.  Each prints the mean
-HIP-event time per launch."""
+HIP-event time per launch.  vendor: the same square product in the vendor
+libraries (torch.matmul, which calls hipBLASLt / rocBLAS) in binary64, FP32
+and bfloat16, for comparison only: nothing in libmm calls them."""
 from __future__ import annotations
 
 import argparse
@@ -79,9 +82,31 @@ def gemm(method, n, variant, reps, sweep=None):
               f"{2.0 * n ** 3 / (ms * 1e-3) / 1e12:.1f} TFLOP/s", flush=True)
 
 
+def vendor_rates(torch, n, reps=10):
+    """TFLOP/s of torch.matmul on n x n operands (uniform on [-0.5, 0.5),
+    seed 0) per dtype, HIP events over `reps` launches after 3 warm-ups."""
+    g = torch.Generator(device="cuda").manual_seed(0)
+    res = {}
+    for name, dt in (("f64", torch.float64), ("f32", torch.float32), ("bf16", torch.bfloat16)):
+        a = torch.rand(n, n, dtype=dt, device="cuda", generator=g) - 0.5
+        b = torch.rand(n, n, dtype=dt, device="cuda", generator=g) - 0.5
+        c = torch.empty(n, n, dtype=dt, device="cuda")
+        ms = _events(torch, lambda: torch.matmul(a, b, out=c), reps, warmup=3)
+        res[name] = {"ms": ms, "tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12}
+        del a, b, c
+    torch.cuda.empty_cache()
+    return res
+
+
+def vendor(n, reps):
+    import torch
+    for name, r in vendor_rates(torch, n, reps).items():
+        print(f"vendor {name} n={n}: {r['ms']:.4f} ms per launch, {r['tflops']:.1f} TFLOP/s", flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("workload", choices=["grouped", "gemm"])
+    ap.add_argument("workload", choices=["grouped", "gemm", "vendor"])
     ap.add_argument("--method", default="f64", choices=["f64", "f32", "split3", "split6"])
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--schedule", type=int, default=None)
@@ -94,6 +119,8 @@ def main(argv=None):
         if a.method == "f64":
             ap.error("the grouped batch has FP32 inputs: --method f32, split3 or split6")
         grouped(a.method, a.variant, a.schedule, a.reps, a.sweep)
+    elif a.workload == "vendor":
+        vendor(a.n, a.reps)
     else:
         gemm(a.method, a.n, a.variant, a.reps, a.sweep)
 

@@ -39,7 +39,7 @@ def test_peak_library_exports_its_header():
     from paper_2408_15384_amd import build as B
     peak = ctypes.CDLL(B.PEAK_LIB)
     names = declared_functions(os.path.join(ROOT, "include", "mm_peak.h"))
-    assert names == ["mm_peak_mfma"]
+    assert names == ["mm_peak_mfma", "mm_peak_overlap"]
     assert all(hasattr(peak, n) for n in names)
     fn = peak.mm_peak_mfma
     fn.restype = ctypes.c_int32
@@ -48,6 +48,13 @@ def test_peak_library_exports_its_header():
     assert fn(0, 12, 1, 1, 1024, None) == -1     # unsupported chain count
     assert fn(0, 8, 0, 1, 1024, None) == -1      # no blocks
     assert fn(0, 8, 1, 1, None, None) == -1      # no output
+    ov = peak.mm_peak_overlap
+    ov.restype = ctypes.c_int32
+    ov.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    assert ov(3, 1, 1, 1024, None) == -1         # bad role
+    assert ov(0, 0, 1, 1024, None) == -1         # no blocks
+    assert ov(0, 1, 0, 1024, None) == -1         # no iterations
+    assert ov(0, 1, 1, None, None) == -1         # no output
 
 
 def test_status_strings(lib):

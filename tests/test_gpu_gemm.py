@@ -451,8 +451,9 @@ def test_f32_and_split_8192_rows(mm, kind):
 
 
 def test_peak_probe_runs(mm):
-    """The MFMA-only measurement aid launches for every dtype and writes its
-    output (it computes no product, so only completion is checked)."""
+    """The measurement aids (MFMA-only throughput, matrix/vector overlap)
+    launch for every dtype and role and write their output (they compute no
+    product, so only completion is checked)."""
     import ctypes
     from paper_2408_15384_amd import build as B
     lib = ctypes.CDLL(B.PEAK_LIB)
@@ -466,3 +467,12 @@ def test_peak_probe_runs(mm):
             assert fn(dtype, chains, 4, 16, out.data_ptr(), torch.cuda.current_stream().cuda_stream) == 0
             torch.cuda.synchronize()
             assert torch.isfinite(out).all()
+    ov = lib.mm_peak_overlap
+    ov.restype = ctypes.c_int32
+    ov.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    out = torch.full((4 * 512,), float("nan"), dtype=torch.float32, device="cuda")
+    for role in (0, 1, 2):
+        out.fill_(float("nan"))
+        assert ov(role, 4, 16, out.data_ptr(), torch.cuda.current_stream().cuda_stream) == 0
+        torch.cuda.synchronize()
+        assert torch.isfinite(out).all()
