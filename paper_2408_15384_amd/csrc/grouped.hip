@@ -237,21 +237,28 @@ struct StaticSeq {
 // one-workgroup-per-tile form places them -- drawing positions from the XCD's
 // own counter, so tiles that share a problem's panels share an L2.  The grid
 // is a multiple of 8.
+// Thread 0 draws position i + 1's ticket in draw(i) but writes it to LDS only
+// when tile(i + 1) is asked for, so the atomic's latency passes while the
+// workgroup multiplies instead of holding up the next barrier.
 struct TicketSeq {
-    int *counter;     // 8 counters, one per XCD
-    int64_t *ring;    // LDS, 8 entries: tile of sequence position i at i % 8
+    int *counter;       // 8 counters, one per XCD
+    int64_t *ring;      // LDS, 8 entries: tile of sequence position i at i % 8
+    int pending = -1;   // thread 0: the position whose ticket is in flight
+    int ticket = 0;     // thread 0: that ticket
     __device__ __forceinline__ static int64_t chunked(int64_t xcd, int64_t local) {
         return ((local / kChunk) * 8 + xcd) * kChunk + local % kChunk;
     }
     __device__ __forceinline__ int64_t tile(int i) const {
         if (i == 0) return chunked(blockIdx.x % 8, blockIdx.x / 8);
+        if (threadIdx.x == 0 && pending == i)
+            ring[i & 7] = chunked(blockIdx.x % 8, (int64_t)(gridDim.x / 8) + ticket);
         __syncthreads();   // thread 0's write of position i is visible
         return uniform(ring[i & 7]);
     }
     __device__ __forceinline__ void draw(int i) {
         if (threadIdx.x == 0) {
-            const int x = blockIdx.x % 8;
-            ring[(i + 1) & 7] = chunked(x, (int64_t)(gridDim.x / 8) + atomicAdd(counter + x, 1));
+            ticket = atomicAdd(counter + blockIdx.x % 8, 1);
+            pending = i + 1;
         }
     }
 };
@@ -351,9 +358,10 @@ struct KernelInfo {
     bool stream = false;   // a streamed persistent form exists (ring-fused split tiles)
 };
 
-// Ring-fused split tiles (the only ones with a streamed persistent form).
+// Ring-fused split tiles with one K step in flight (the only ones with a
+// streamed persistent form).
 template <typename T, typename = void> struct has_ring : std::false_type {};
-template <typename T> struct has_ring<T, std::void_t<decltype(T::RS)>> : std::true_type {};
+template <typename T> struct has_ring<T, std::void_t<decltype(T::RS)>> : std::bool_constant<T::RS == 1> {};
 
 template <typename TG, typename T>
 static KernelPtr dense_kernel(int form) {

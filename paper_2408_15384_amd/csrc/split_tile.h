@@ -1017,15 +1017,22 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
 
     // ---------------------------------------------------------------- stream
     // A persistent workgroup's tiles as one stream of K steps: the load side
-    // runs RS steps ahead of the products and crosses into the next tile
+    // runs one step ahead of the products and crosses into the next tile
     // while the current one is still being multiplied, so a tile's first
     // loads are in flight when its predecessor ends.  Each tile's products,
     // order and recombination are those of run_fused (the same bits).
     // `seq` names the workgroup's i-th tile (seq.tile(i), >= total at the end;
-    // seq.draw(i) is called once the i-th tile is opened for loading, so that
-    // a dynamic sequence can fetch the (i+1)-th).  decode(t, g) fills tile t's
-    // geometry; every tile must satisfy ring_ok (the caller checks the batch).
-    // A tile without K steps (K == 0) runs one step of zeros.
+    // seq.draw(i), called at the start of the step after the i-th tile was
+    // opened for loading, lets a dynamic sequence fetch the (i+1)-th).
+    // decode(t, g) fills tile t's geometry; every tile must satisfy ring_ok
+    // (the caller checks the batch).  A tile without K steps (K == 0) runs one
+    // step of zeros.  Per step, in order: [draw], the step's loads, the
+    // products of the step before, [opening the next tile: its decode's
+    // latency overlaps the loads in flight], the split of the loaded step,
+    // [the end of a tile: its epilogue], one barrier.  Each tile is decoded
+    // once: the compute side takes the geometry the load side decoded.  The
+    // stream keeps one step in flight (RS == 1).
+
     struct Geo {
         const float *A, *B;
         void *C;
@@ -1039,20 +1046,21 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
         Offs o;
     };
 
-    struct ComputeCursor {
+    // What the products and the epilogue need of a tile.
+    struct ComputeTile {
         void *C;
-        int64_t ldc, M, N, m0, n0, nk, k, t;
-        int i;
+        int64_t ldc, M, N, m0, n0, nk;
     };
 
     static __device__ __forceinline__ int64_t steps_of(int64_t K) { return K > 0 ? (K + BK - 1) / BK : 1; }
 
+    // Open sequence position i for loading; its compute geometry goes to `ct`.
     template <typename Seq, typename Decode>
-    static __device__ __forceinline__ void open_load(LoadCursor &L, int i, int64_t total, Seq &seq, Decode &decode) {
+    static __device__ __forceinline__ void open_load(LoadCursor &L, int i, int64_t total, Seq &seq, Decode &decode,
+                                                     ComputeTile &ct) {
         L.i = i;
         L.t = seq.tile(i);
         if (L.t >= total) return;
-        seq.draw(i);
         Geo g;
         decode(L.t, g);
         const int64_t m0 = g.tm * BM, n0 = g.tn * BN;
@@ -1066,16 +1074,16 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
         L.rows_left = (int)((g.M - m0) < BM ? (g.M - m0) : BM);
         L.cols_left = (int)((g.N - n0) < BN ? (g.N - n0) : BN);
         offsets(L.lda, L.ldb, L.rows_left, L.cols_left, L.o);
+        ct = ComputeTile{g.C, g.ldc, g.M, g.N, m0, n0, L.nk};
     }
 
     // Request the load cursor's next step into R (kvalid: valid K entries of
-    // that step, 0 for the zero step of a K == 0 tile) and advance.
-    template <typename Seq, typename Decode>
-    static __device__ __forceinline__ void next_load(LoadCursor &L, Regs &R, int64_t &kvalid, int64_t total, Seq &seq,
-                                                     Decode &decode) {
+    // that step, 0 for the zero step of a K == 0 tile, -1 past the end of the
+    // stream) and advance; returns whether that was the tile's last step.
+    static __device__ __forceinline__ bool next_load(LoadCursor &L, Regs &R, int64_t &kvalid, int64_t total) {
         if (L.t >= total) {
-            kvalid = -1;   // past the end of the stream: nothing to put
-            return;
+            kvalid = -1;
+            return false;
         }
         if (L.K > 0) {
             load(R, L.o, L.Ap, L.lda, L.Bp, L.ldb, L.rows_left, L.cols_left, L.K, L.k);
@@ -1083,31 +1091,13 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
         } else {
             kvalid = 0;
         }
-        if (++L.k == L.nk) open_load(L, L.i + 1, total, seq, decode);
-    }
-
-    template <typename Seq, typename Decode>
-    static __device__ __forceinline__ bool open_compute(ComputeCursor &Cc, int i, int64_t total, Seq &seq,
-                                                        Decode &decode) {
-        Cc.i = i;
-        Cc.t = seq.tile(i);
-        if (Cc.t >= total) return false;
-        Geo g;
-        decode(Cc.t, g);
-        Cc.C = g.C;
-        Cc.ldc = g.ldc;
-        Cc.M = g.M;
-        Cc.N = g.N;
-        Cc.m0 = g.tm * BM;
-        Cc.n0 = g.tn * BN;
-        Cc.nk = steps_of(g.K);
-        Cc.k = 0;
-        return true;
+        return ++L.k == L.nk;
     }
 
     template <typename Seq, typename Decode>
     static __device__ __forceinline__ void run_stream(int64_t total, int c_is_f64, Seq seq, Decode decode,
                                                       uint16_t *smem) {
+        static_assert(RS == 1, "the stream keeps one step in flight");
         f32x4 lead[FM][FN], corr[FM][FN];
 #pragma unroll
         for (int fm = 0; fm < FM; ++fm)
@@ -1116,43 +1106,67 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
                 lead[fm][fn] = f32x4{0, 0, 0, 0};
                 corr[fm][fn] = f32x4{0, 0, 0, 0};
             }
-        ComputeCursor Cc;
-        if (!open_compute(Cc, 0, total, seq, decode)) return;
+        // compute geometry of opened tiles, by sequence parity: the load side
+        // is at most two tiles ahead of the products (one step, and a tile
+        // of a single step)
+        ComputeTile even, odd;
         LoadCursor L;
-        open_load(L, 0, total, seq, decode);
-        Regs R[RS];
-        int64_t kv[RS];
-#pragma unroll
-        for (int r = 0; r < RS; ++r) {
-            kv[r] = -1;
-            next_load(L, R[r], kv[r], total, seq, decode);
+        open_load(L, 0, total, seq, decode, even);
+        if (L.t >= total) return;
+        ComputeTile cur = even;
+        int ci = 0;              // sequence position of the tile being multiplied
+        int opened = 1;          // positions opened that hold a tile
+        int64_t ck = 0;          // its steps done
+        bool draw = true;        // position L.i was opened: fetch position L.i + 1 next step
+        Regs R;
+        int64_t kv;
+        seq.draw(0);
+        draw = false;
+        if (next_load(L, R, kv, total)) {
+            ComputeTile ct;
+            open_load(L, 1, total, seq, decode, ct);
+            if (L.t < total) {
+                odd = ct;
+                ++opened;
+                draw = true;
+            }
         }
-        put(smem, R[0], kv[0]);
+        put(smem, R, kv);
         __syncthreads();
-        bool live = true;
-        for (int64_t g = 0; live; g += RS) {
-#pragma unroll
-            for (int r = 0; r < RS; ++r) {
-                if (live) {
-                    // stream step g + r is in LDS buffer (g + r) & 1; slot r is free
-                    next_load(L, R[r], kv[r], total, seq, decode);
-                    // products of this step, split of the next stream step (if any)
-                    step(smem + ((g + r) & 1) * STAGE, smem + ((g + r + 1) & 1) * STAGE, R[(r + 1) % RS],
-                         kv[(r + 1) % RS], lead, corr);
-                    if (++Cc.k == Cc.nk) {
-                        epilogue(lead, corr, Cc.C, Cc.ldc, c_is_f64, Cc.M, Cc.N, Cc.m0, Cc.n0);
-#pragma unroll
-                        for (int fm = 0; fm < FM; ++fm)
-#pragma unroll
-                            for (int fn = 0; fn < FN; ++fn) {
-                                lead[fm][fn] = f32x4{0, 0, 0, 0};
-                                corr[fm][fn] = f32x4{0, 0, 0, 0};
-                            }
-                        live = open_compute(Cc, Cc.i + 1, total, seq, decode);
-                    }
-                    __syncthreads();
+        for (int64_t g = 0;; ++g) {
+            // stream step g is in LDS buffer g & 1
+            if (draw) {
+                seq.draw(L.i);
+                draw = false;
+            }
+            const bool crossed = next_load(L, R, kv, total);
+            const uint16_t *cb = smem + (g & 1) * STAGE;
+            compute(cb, cb + NP * A_PLANE, lead, corr);
+            if (crossed) {
+                ComputeTile ct;
+                open_load(L, L.i + 1, total, seq, decode, ct);
+                if (L.t < total) {
+                    if (L.i & 1) odd = ct;
+                    else even = ct;
+                    ++opened;
+                    draw = true;
                 }
             }
+            if (kv >= 0) put(smem + ((g + 1) & 1) * STAGE, R, kv);
+            if (++ck == cur.nk) {
+                epilogue(lead, corr, cur.C, cur.ldc, c_is_f64, cur.M, cur.N, cur.m0, cur.n0);
+#pragma unroll
+                for (int fm = 0; fm < FM; ++fm)
+#pragma unroll
+                    for (int fn = 0; fn < FN; ++fn) {
+                        lead[fm][fn] = f32x4{0, 0, 0, 0};
+                        corr[fm][fn] = f32x4{0, 0, 0, 0};
+                    }
+                if (++ci >= opened) break;   // the load side found no further tile
+                cur = (ci & 1) ? odd : even;
+                ck = 0;
+            }
+            __syncthreads();
         }
     }
 };
