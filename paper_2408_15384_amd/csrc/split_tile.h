@@ -1022,8 +1022,9 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
     // loads are in flight when its predecessor ends.  Each tile's products,
     // order and recombination are those of run_fused (the same bits).
     // `seq` names the workgroup's i-th tile (seq.tile(i), >= total at the end;
-    // seq.draw(i), called at the start of the step after the i-th tile was
-    // opened for loading, lets a dynamic sequence fetch the (i+1)-th).
+    // seq.draw(i), called at the start of the load side's second-to-last step
+    // of the i-th tile, or its only one, lets a dynamic sequence fetch the
+    // (i+1)-th).
     // decode(t, g) fills tile t's geometry; every tile must satisfy ring_ok
     // (the caller checks the batch).  A tile without K steps (K == 0) runs one
     // step of zeros.  Per step, in order: [draw], the step's loads, the
@@ -1117,27 +1118,33 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
         int ci = 0;              // sequence position of the tile being multiplied
         int opened = 1;          // positions opened that hold a tile
         int64_t ck = 0;          // its steps done
-        bool draw = true;        // position L.i was opened: fetch position L.i + 1 next step
+        // Position L.i + 1 is drawn two steps before the load side needs it,
+        // not when L.i opens: claimed early, a workgroup's next tile would
+        // wait a whole tile, and the tiles in flight on an XCD would spread
+        // over twice the stretch of the tile map (fewer shared panels in L2).
+        bool drawn = false;
         Regs R;
         int64_t kv;
-        seq.draw(0);
-        draw = false;
+        if (L.nk <= 2) {
+            seq.draw(0);
+            drawn = true;
+        }
         if (next_load(L, R, kv, total)) {
             ComputeTile ct;
             open_load(L, 1, total, seq, decode, ct);
+            drawn = false;
             if (L.t < total) {
                 odd = ct;
                 ++opened;
-                draw = true;
             }
         }
         put(smem, R, kv);
         __syncthreads();
         for (int64_t g = 0;; ++g) {
             // stream step g is in LDS buffer g & 1
-            if (draw) {
+            if (!drawn && L.t < total && L.nk - L.k <= 2) {
                 seq.draw(L.i);
-                draw = false;
+                drawn = true;
             }
             const bool crossed = next_load(L, R, kv, total);
             const uint16_t *cb = smem + (g & 1) * STAGE;
@@ -1145,11 +1152,11 @@ struct SplitTileFusedRing : SplitTileFused<NPROD, BM_, BN_, WM_, WN_> {
             if (crossed) {
                 ComputeTile ct;
                 open_load(L, L.i + 1, total, seq, decode, ct);
+                drawn = false;
                 if (L.t < total) {
                     if (L.i & 1) odd = ct;
                     else even = ct;
                     ++opened;
-                    draw = true;
                 }
             }
             if (kv >= 0) put(smem + ((g + 1) & 1) * STAGE, R, kv);
