@@ -184,7 +184,9 @@ mm_status mm_gemm_f32(int64_t M, int64_t N, int64_t K, const float *A, int64_t l
     if ((s = check_arch()) != MM_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     if (K == 0) MM_HIP(launch_fill_zero(C, M, N, ldc, 4, st));
-    else MM_HIP(launch_gemm_f32(select_variant(MM_F32, M, N, K), M, N, K, A, lda, B, ldb, C, ldc, st));
+    else MM_HIP(launch_gemm_f32(variant_for_operands(MM_F32, select_variant(MM_F32, M, N, K),
+                                                     direct_operands(A, lda, B, ldb, N, 4)),
+                                M, N, K, A, lda, B, ldb, C, ldc, st));
     return MM_OK;
     MM_GUARD_END
 }
@@ -331,7 +333,8 @@ mm_status mm_gemm_ex(mm_method method, mm_op opa, mm_op opb, int64_t M, int64_t 
             lb = N;
         }
         if (err == hipSuccess) {
-            const int v = select_variant(method, M, N, K);
+            const int v = variant_for_operands(method, select_variant(method, M, N, K),
+                                               direct_operands(a, la, b, lb, N, (int64_t)e));
             err = method == MM_F64 ? launch_gemm_f64(v, M, N, K, (const double *)a, la, (const double *)b, lb,
                                                      (double *)C, ldc, st)
                                    : launch_gemm_f32(v, M, N, K, (const float *)a, la, (const float *)b, lb,

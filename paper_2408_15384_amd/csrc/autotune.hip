@@ -62,13 +62,15 @@ struct Candidate {
     bool plane_pass;
 };
 
-// The large binary64 and FP32 tiles are the 16-wave 256x128 rings (64x32 wave
-// tiles, four waves per SIMD): equal to the 8-wave ones at 8192, 2-8% faster
-// at 3072-6144.
+// The large binary64 tile is the 16-wave 256x128 ring (64x32 wave tiles, four
+// waves per SIMD): equal to the 8-wave one at 8192, 2-8% faster at 3072-6144.
+// FP32 adds the 16-wave 256x256 ring (64x64 wave tiles: half the fragment
+// reads and barriers per product of the 256x128 one; 146.5 against 142.6
+// TFLOP/s at 8192, +2.7% at 4096 and 16384).
 const Candidate kF64Cand[] = {{15, 256, 128, 71.0, false}, {3, 128, 64, 56.5, false}, {13, 64, 64, 64.1, false},
                               {14, 32, 32, 52.0, false}};
-const Candidate kF32Cand[] = {{13, 256, 128, 142.6, false}, {3, 128, 128, 126.5, false}, {8, 64, 64, 141.0, false},
-                              {10, 32, 32, 95.0, false}};
+const Candidate kF32Cand[] = {{14, 256, 256, 146.5, false}, {13, 256, 128, 142.6, false}, {3, 128, 128, 126.5, false},
+                              {8, 64, 64, 141.0, false}, {10, 32, 32, 95.0, false}};
 const Candidate kSplit3Unfused[] = {{14, 256, 128, 438.0, true}, {6, 128, 128, 364.0, true}, {8, 64, 64, 319.0, true}};
 const Candidate kSplit6Unfused[] = {{9, 256, 128, 214.0, true}, {6, 128, 128, 190.0, true}, {8, 64, 64, 100.4, true}};
 // Fused candidates are the ring forms with one K step in flight and paired
@@ -157,6 +159,15 @@ int select_grouped(const mm_problem *probs, int count, mm_method method, int *sc
 void store_grouped(const mm_problem *probs, int count, mm_method method, int variant, int schedule, double ms) {
     std::lock_guard<std::mutex> lock(g_mu);
     g_cache[grouped_key(probs, count, method)] = Entry{variant, ms, schedule};
+}
+
+// The FP32 256x256 ring's register-staged body (which runs operands the
+// direct loads cannot take) holds more than the 128 registers its occupancy
+// allows and spills: 101 against 131 TFLOP/s for the 256x128 variant's at
+// 8192.  Such operands run the 256x128 variant instead.
+int variant_for_operands(mm_method method, int variant, bool direct_ok) {
+    if (!direct_ok && method == MM_F32 && variant == 14) return 13;
+    return variant;
 }
 
 int select_variant(mm_method method, int64_t M, int64_t N, int64_t K) {
