@@ -335,7 +335,6 @@ struct TileGemmDirect {
                 const int c = swz_b(row, Q % B_CPR);
                 int64_t gc = n0 + c * VEC;
                 // chunks past N re-read the last chunk holding valid columns
-                // (vector-aligned, so every load stays 16-byte aligned)
                 const int64_t last = (N - 1) / VEC * VEC;
                 gc = gc < N ? gc : last;
                 voff[j] = (uint32_t)((row * ldb + (gc - n0)) * (int64_t)sizeof(T));
@@ -454,14 +453,22 @@ struct TileGemmDirect {
         __builtin_amdgcn_s_waitcnt((N_ & 15) | (7 << 4) | (15 << 8) | ((N_ >> 4) << 14));
     }
 
+    // Operands the ring takes: N of at least one vector, bases aligned to the
+    // element, and a slice's per-lane offsets within the 31-bit buffer range.
+    // Leading dimensions need not be multiples of the vector nor bases
+    // 16-byte aligned: the direct-to-LDS load fetches its 16 bytes at any
+    // element-aligned offset (checked on the GPU with an in-bounds probe at
+    // offsets of 0-3 floats), so a row that starts mid-vector is read as
+    // chunks that start there; a chunk that runs past the end of a row brings
+    // the next row's first elements, which only meet the columns of B past N
+    // (never stored) or, past K, the LDS slots the ragged last step clears.
     static __device__ __forceinline__ bool eligible(const T *A, int64_t lda, const T *B, int64_t ldb, int64_t N,
                                                     int64_t K) {
-        // the per-lane offsets within a slice must fit the buffer range
         const int64_t a_span = ((int64_t)(BM - 1) * lda + BK) * (int64_t)sizeof(T);
         const int64_t b_span = ((int64_t)(BK - 1) * ldb + BN) * (int64_t)sizeof(T);
         (void)K;
-        return N >= VEC && lda % VEC == 0 && ldb % VEC == 0 &&
-               ((uintptr_t)A % 16 == 0) && ((uintptr_t)B % 16 == 0) && a_span < 0x7fffffff && b_span < 0x7fffffff;
+        return N >= VEC && ((uintptr_t)A % sizeof(T) == 0) && ((uintptr_t)B % sizeof(T) == 0) &&
+               a_span < 0x7fffffff && b_span < 0x7fffffff;
     }
 
     // The K loop over the ring.  RAGGED (K not a multiple of BK, or N not a

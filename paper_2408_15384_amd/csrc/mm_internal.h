@@ -192,12 +192,11 @@ int select_variant(mm_method method, int64_t M, int64_t N, int64_t K);
 // The variant to run for operands the direct global-to-LDS loads can take
 // (direct_ok) or not: a variant whose fallback body spills is swapped.
 int variant_for_operands(mm_method method, int variant, bool direct_ok);
-// Whether the direct tiles take these operands: 16-byte aligned bases,
-// leading dimensions a multiple of the 16-byte vector, N at least one vector,
-// and a tile's rows of A (256) and K step of B (32) within 31-bit offsets.
+// Whether the direct tiles take these operands: element-aligned bases, N at
+// least one 16-byte vector, and a tile's rows of A (256) and K step of B (32)
+// within 31-bit offsets.
 inline bool direct_operands(const void *A, int64_t lda, const void *B, int64_t ldb, int64_t N, int64_t elem) {
-    const int64_t vec = 16 / elem;
-    return N >= vec && lda % vec == 0 && ldb % vec == 0 && (uintptr_t)A % 16 == 0 && (uintptr_t)B % 16 == 0 &&
+    return N >= 16 / elem && (uintptr_t)A % elem == 0 && (uintptr_t)B % elem == 0 &&
            256 * lda * elem < 0x7fffffffLL && 32 * ldb * elem < 0x7fffffffLL;
 }
 // Variant and schedule of a grouped launch: the cache entry of the batch's
