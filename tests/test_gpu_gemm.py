@@ -103,13 +103,14 @@ def test_direct_tile_shapes(mm, method, shape):
         assert np.array_equal(host(C).astype(np.float64), oracle.gemm(Ai, Bi)), f"variant {v}"
 
 
-def _padded_view(X, ld, fill=float("nan"), tight=False):
+def _padded_view(X, ld, fill=float("nan"), tight=False, offset=0):
     """X (host) as a device view with leading dimension ld in a buffer whose
-    padding holds `fill`; tight: the buffer ends at X's last element."""
+    padding holds `fill`, starting `offset` elements into it; tight: the
+    buffer ends at X's last element."""
     rows, cols = X.shape
-    size = (rows - 1) * ld + cols if tight else rows * ld + 64
+    size = offset + ((rows - 1) * ld + cols if tight else rows * ld + 64)
     buf = torch.full((size,), fill, dtype=torch.float64 if X.dtype == np.float64 else torch.float32, device="cuda")
-    v = torch.as_strided(buf, (rows, cols), (ld, 1))
+    v = torch.as_strided(buf, (rows, cols), (ld, 1), offset)
     v.copy_(torch.from_numpy(np.ascontiguousarray(X)).cuda())
     return v
 
@@ -133,6 +134,32 @@ def test_direct_tile_any_k_and_n(mm, method, shape):
     for k2, (A, B) in ((kind, I.pair(kind, M, N, K, seed=M + K)),
                        ("int", I.pair("int_f64" if method == "f64" else "int_f32", M, N, K, seed=M + K + 1))):
         dA, dB = _padded_view(A, lda), _padded_view(B, ldb, tight=True)
+        for v in range(mm.variant_count(method)):
+            C = torch.full((M, N), float("nan"), dtype=dA.dtype, device="cuda")
+            mm.gemm_variant(method, v, dA, dB, C)
+            got = host(C).astype(np.float64)
+            if k2 == "int":
+                assert np.array_equal(got, oracle.gemm(A, B)), f"variant {v}"
+            else:
+                assert_within_bound(got, A, B, u)
+
+
+@pytest.mark.parametrize("method", ["f64", "f32"])
+@pytest.mark.parametrize("shape", [(257, 131, 45), (70, 67, 49), (300, 260, 64), (33, 8, 250)])
+def test_direct_tile_any_leading_dimension(mm, method, shape):
+    """The direct-to-LDS tiles on leading dimensions that are not multiples of
+    the 16-byte vector and on bases one element past a 16-byte boundary: a
+    row then starts mid-vector, and its last chunk runs into the next row's
+    first elements (NaN padding here) -- past N they meet only columns that
+    are not stored, past K the cleared slots.  Every variant within the bound
+    of the oracle; integer inputs bit-exact."""
+    M, N, K = shape
+    u = oracle.U_F64 if method == "f64" else oracle.U_F32
+    kind = "uniform_f64" if method == "f64" else "uniform_f32"
+    lda, ldb = K + 1, N + 3
+    for k2, (A, B) in ((kind, I.pair(kind, M, N, K, seed=M + N)),
+                       ("int", I.pair("int_f64" if method == "f64" else "int_f32", M, N, K, seed=M + N + 1))):
+        dA, dB = _padded_view(A, lda, offset=1), _padded_view(B, ldb, tight=True, offset=1)
         for v in range(mm.variant_count(method)):
             C = torch.full((M, N), float("nan"), dtype=dA.dtype, device="cuda")
             mm.gemm_variant(method, v, dA, dB, C)
