@@ -274,10 +274,10 @@ struct TileGemm {
 // C that are not stored).  Any K: a last step past K reads through byte
 // ranges that end at the operands' last valid elements and clears A's columns
 // past K in LDS (clear_a_tail); column chunks of B reaching past N feed only
-// entries of C that are not stored.  It needs lda and ldb multiples of the
-// 16-byte vector, N at least one vector, 16-byte aligned bases and K slices
-// whose lane offsets fit 31 bits; other problems run the register-staged tile
-// (same tile shape) in the same kernel.
+// entries of C that are not stored.  It takes any leading dimension and
+// element-aligned bases (see eligible()); it needs N of at least one vector
+// and K slices whose lane offsets fit 31 bits, and other problems run the
+// register-staged tile (same tile shape) in the same kernel.
 typedef __attribute__((address_space(3))) void mm_lvoid;
 
 template <typename T, int BM_, int BN_, int BK_, int WM_, int WN_, int STAGES_>
