@@ -213,6 +213,47 @@ def precision_section(torch, mm, n, steps, warmup):
     return out
 
 
+def sizes_section(torch, mm, sizes=((1024, 30), (4096, 10))):
+    """The plain binary64 product at the other sizes of the headline's
+    configuration (N = 1024 and 4096; 8192 is the headline): HIP-event
+    throughput on uniform [-1, 1) inputs, each result checked against the
+    oracle on its first rows (normwise and per entry within the bound), and
+    the integer-valued inputs (uniform integers in [-8, 8]) bit-exact against
+    the oracle -- the whole product at 1024, 64 rows spread over the tile rows
+    at 4096."""
+    import oracle
+    out = {}
+    for n, steps in sizes:
+        A, B = I.pair("uniform_f64", n, n, n, seed=0)
+        dA, dB = torch.from_numpy(A).cuda(), torch.from_numpy(B).cuda()
+        C = torch.empty((n, n), dtype=torch.float64, device="cuda")
+        wall, ev, med, mn = timed_steps(torch, lambda: mm.gemm_f64(dA, dB, C), steps, 3)
+        tf = 2.0 * n ** 3 / (ev * 1e-3) / 1e12
+        Ch = C.cpu().numpy()
+        R = oracle.gemm(A[:4], B)
+        bound = oracle.elementwise_bound(oracle.abs_product(A[:4], B), n, oracle.U_F64)
+        res = {"ms": ev, "tflops": tf, "frac_of_peak": tf / PEAK["f64"],
+               "variant": mm.select_variant("f64", n, n, n),
+               "normwise_err_vs_oracle_rows0_3": float(np.linalg.norm(Ch[:4] - R) / np.linalg.norm(R)),
+               "within_bound_rows0_3": bool(np.all(np.abs(Ch[:4] - R) <= bound))}
+        Ai, Bi = I.pair("int_f64", n, n, n, seed=1)
+        dAi, dBi = torch.from_numpy(Ai).cuda(), torch.from_numpy(Bi).cuda()
+        mm.gemm_f64(dAi, dBi, C)
+        Ci = C.cpu().numpy()
+        if n <= 1024:
+            rows = np.arange(n)
+        else:
+            rows = np.unique(np.linspace(0, n - 1, 64).astype(np.int64))
+        res["int_bit_exact_rows"] = int(len(rows))
+        res["int_bit_exact"] = bool(np.array_equal(Ci[rows], oracle.gemm(Ai[rows], Bi)))
+        out[str(n)] = res
+        log(f"  binary64 {n}: {ev:.3f} ms {tf:.1f} TFLOP/s ({tf / PEAK['f64']:.1%}), integer inputs bit-exact on "
+            f"{len(rows)} rows: {res['int_bit_exact']}")
+        del dA, dB, dAi, dBi, C
+        torch.cuda.empty_cache()
+    return out
+
+
 def grouped_section(torch, mm, reps=10):
     shapes = [tuple(int(v) for v in s) for s in I.grouped_shapes(512, 32, 1024, seed=0)]
     As, Bs, Cs = [], [], []
@@ -668,9 +709,9 @@ def main():
     ap.add_argument("--steps", type=int, default=15)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=8192)
-    ap.add_argument("--sections", default="peak,precision,grouped,serving,strassen,shard,layouts,paper,vendor",
-                    help="comma list of sections to run after the headline (peak, precision, grouped, serving, strassen, shard, layouts, "
-                         "paper, vendor; "
+    ap.add_argument("--sections", default="peak,sizes,precision,grouped,serving,strassen,shard,layouts,paper,vendor",
+                    help="comma list of sections to run after the headline (peak, sizes, precision, grouped, serving, strassen, "
+                         "shard, layouts, paper, vendor; "
                          "or none)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -729,6 +770,9 @@ def main():
     if "peak" in sections:
         log("peak: MFMA-only throughput per dtype")
         line["mfma_peak"] = peak_section(torch, achieved)
+    if "sizes" in sections:
+        log("sizes: binary64 at N = 1024 and 4096")
+        line["sizes"] = sizes_section(torch, mm)
     if "precision" in sections:
         log("precision: FP32 vs split-bf16 at N=8192")
         line["precision"] = precision_section(torch, mm, n, args.steps, args.warmup)
