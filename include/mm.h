@@ -310,7 +310,9 @@ mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out
  * schedule instead of the autotuned choice.  schedule: 0 = problems in the
  * given order, a persistent grid takes tiles by a fixed stride; 1 = heaviest
  * problems (largest M*N*K) first, fixed stride; 2 = heaviest first, the
- * persistent grid pulls tiles from a device work counter; 3 = heaviest first,
+ * persistent grid pulls tiles from device work counters (one per XCD, each
+ * XCD walking its own share of the tile map, for the ring-fused split tiles;
+ * one for the others); 3 = heaviest first,
  * one workgroup per tile, dispatched by the hardware.  Every
  * schedule gives the same bits.  An existing plan must have been built with
  * the same variant and schedule.
