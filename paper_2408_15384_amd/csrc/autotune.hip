@@ -67,8 +67,12 @@ struct Candidate {
 // FP32 adds the 16-wave 256x256 ring (64x64 wave tiles: half the fragment
 // reads and barriers per product of the 256x128 one; 146.5 against 142.6
 // TFLOP/s at 8192, +2.7% at 4096 and 16384).
+// The 64x32 ring runs at 0.87x the 64x64 ring's rate on a full grid (2048:
+// 293 against 255 us) but splits the work finer, so it wins where the 64x64
+// grid leaves its last round of CUs mostly empty (1536: 131 against 147 us,
+// 1792: 209 against 221).
 const Candidate kF64Cand[] = {{15, 256, 128, 71.0, false}, {3, 128, 64, 56.5, false}, {7, 64, 64, 67.5, false},
-                              {14, 32, 32, 52.0, false}};
+                              {14, 32, 32, 52.0, false}, {16, 64, 32, 60.0, false}};
 const Candidate kF32Cand[] = {{14, 256, 256, 146.5, false}, {13, 256, 128, 142.6, false}, {3, 128, 128, 126.5, false},
                               {8, 64, 64, 141.0, false}, {10, 32, 32, 95.0, false}};
 const Candidate kSplit3Unfused[] = {{14, 256, 128, 438.0, true}, {6, 128, 128, 364.0, true}, {8, 64, 64, 319.0, true}};
@@ -87,14 +91,16 @@ template <size_t NC>
 int pick(const Candidate (&c)[NC], int64_t M, int64_t N, int64_t K, int planes) {
     int best = c[0].variant;
     double best_t = 0;
+    bool have = false;
     const double k = (double)std::max<int64_t>(K, 1);
     for (size_t i = 0; i < NC; ++i) {
         const double tiles = (double)((M + c[i].bm - 1) / c[i].bm) * (double)((N + c[i].bn - 1) / c[i].bn);
         double t = std::ceil(tiles / kCUs) * 2.0 * c[i].bm * c[i].bn * k * kCUs / (c[i].rate * 1e12);
         if (c[i].plane_pass) t += ((double)M * k + k * (double)N) * (4.0 + 2.0 * planes) / 5.5e12 + 6e-6;
-        if (i == 0 || t < best_t) {
+        if (!have || t < best_t) {
             best = c[i].variant;
             best_t = t;
+            have = true;
         }
     }
     return best;
