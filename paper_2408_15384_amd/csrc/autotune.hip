@@ -70,11 +70,14 @@ struct Candidate {
 // The 64x32 ring runs at 0.87x the 64x64 ring's rate on a full grid (2048:
 // 293 against 255 us) but splits the work finer, so it wins where the 64x64
 // grid leaves its last round of CUs mostly empty (1536: 131 against 147 us,
-// 1792: 209 against 221).
+// 1792: 209 against 221).  The FP32 32x64 ring does the same for the FP32
+// 64x64 one: even on a grid of equal rounds (2048: 149 against 141 us) it is
+// within 6%, and it wins where it leaves fewer rounds (1536: +14%, 1792: +5%,
+// 2560: +2%).
 const Candidate kF64Cand[] = {{15, 256, 128, 71.0, false}, {3, 128, 64, 56.5, false}, {7, 64, 64, 67.5, false},
                               {14, 32, 32, 52.0, false}, {16, 64, 32, 60.0, false}};
 const Candidate kF32Cand[] = {{14, 256, 256, 146.5, false}, {13, 256, 128, 142.6, false}, {3, 128, 128, 126.5, false},
-                              {8, 64, 64, 141.0, false}, {10, 32, 32, 95.0, false}};
+                              {8, 64, 64, 141.0, false}, {10, 32, 32, 95.0, false}, {15, 32, 64, 134.0, false}};
 const Candidate kSplit3Unfused[] = {{14, 256, 128, 438.0, true}, {6, 128, 128, 364.0, true}, {8, 64, 64, 319.0, true}};
 const Candidate kSplit6Unfused[] = {{9, 256, 128, 214.0, true}, {6, 128, 128, 190.0, true}, {8, 64, 64, 100.4, true}};
 // Fused candidates are the ring forms with one K step in flight and paired

@@ -42,7 +42,8 @@
     X(11, 256, 128, 16, 64, 64, 12)   \
     X(12, 256, 128, 32, 64, 64, 12)   \
     X(13, 256, 128, 32, 64, 32, 12)   \
-    X(14, 256, 256, 32, 64, 64, 12)
+    X(14, 256, 256, 32, 64, 64, 12)   \
+    X(15, 32, 64, 32, 16, 32, 12)
 
 // Split variants carry a seventh field, S: 1 or 2 register stages of global
 // prefetch, or 10 + b: a ring of b LDS buffers fed by direct global-to-LDS
