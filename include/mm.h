@@ -306,20 +306,39 @@ mm_status mm_grouped_plan_info(const mm_grouped_plan *plan, int32_t *variant_out
                                int64_t *tiles_out, int32_t *grid_out, int32_t *uses_graph_out);
 
 /*
- * mm_gemm_grouped_config -- mm_gemm_grouped with an explicit tile variant and
- * schedule instead of the autotuned choice.  schedule: 0 = problems in the
- * given order, a persistent grid takes tiles by a fixed stride; 1 = heaviest
- * problems (largest M*N*K) first, fixed stride; 2 = heaviest first, the
- * persistent grid pulls tiles from device work counters (one per XCD, each
- * XCD walking its own share of the tile map, for the ring-fused split tiles;
- * one for the others); 3 = heaviest first,
- * one workgroup per tile, dispatched by the hardware.  Every
- * schedule gives the same bits.  An existing plan must have been built with
- * the same variant and schedule.
+ * mm_gemm_grouped_config -- mm_gemm_grouped with an explicit tile variant (or
+ * size-class pair, below) and schedule instead of the autotuned choice.
+ * schedule: 0 = problems in the given order, a persistent grid takes tiles by
+ * a fixed stride; 1 = heaviest problems (largest M*N*K) first, fixed stride;
+ * 2 = heaviest first, the persistent grid pulls tiles from device work
+ * counters (one per XCD, each XCD walking its own share of the tile map, for
+ * the ring-fused split tiles; one for the others); 3 = heaviest first, one
+ * workgroup per tile, dispatched by the hardware.  Every schedule gives the
+ * same bits.  An existing plan must have been built with the same variant and
+ * schedule.
  */
 mm_status mm_gemm_grouped_config(const mm_problem *probs, int32_t count, mm_method method,
                                  int32_t variant, int32_t schedule,
                                  mm_grouped_plan **plan_inout, void *stream);
+
+/*
+ * Size-class pairs.  A grouped variant id MM_PAIR_BASE + p, for
+ * p < mm_grouped_pair_count(method), runs each problem of the batch on one
+ * of two tile variants of the same workgroup size (`small` and `large` of
+ * mm_grouped_pair_info): on `small` when its tiles execute at most pct % of
+ * the padded work (rows, columns and K rounded up to the tiles) of `large`'s,
+ * else on `large`.  The choice is a function of (M, N, K) alone, so each
+ * problem's result is identical to the single-problem result of the variant
+ * it ran on.  Accepted wherever a grouped variant is: mm_gemm_grouped_config,
+ * the grouped autotuner (which times every pair beside the single variants)
+ * and the autotune cache.  Split pairs consist of ring-fused variants.
+ * mm_grouped_pair_info: MM_E_INVAL for an unknown method or pair; outputs
+ * nullable.
+ */
+#define MM_PAIR_BASE 64
+int32_t mm_grouped_pair_count(mm_method method);
+mm_status mm_grouped_pair_info(mm_method method, int32_t pair, int32_t *small_out, int32_t *large_out,
+                               int32_t *pct_out);
 
 /* ------------------------------------------------------------------------ */
 /* Tile configurations and the autotuner.                                    */

@@ -88,6 +88,8 @@ EXPORTS = [
     ("mm_gemm_grouped_config", _st, [ctypes.POINTER(Problem), _i32, _st, _i32, _i32, ctypes.POINTER(_p), _p]),
     ("mm_grouped_autotune", _st, [ctypes.POINTER(Problem), _i32, _st, _i32, _i32, ctypes.POINTER(_i32),
                                   ctypes.POINTER(_i32), ctypes.POINTER(_d), _p]),
+    ("mm_grouped_pair_count", _i32, [_st]),
+    ("mm_grouped_pair_info", _st, [_st, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     ("mm_variant_count", _i32, [_st]),
     ("mm_variant_info", _st, [_st, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     ("mm_select_variant", _i32, [_st, _i64, _i64, _i64]),
@@ -326,6 +328,22 @@ def variant_info(method, variant: int):
     check(lib().mm_variant_info(METHODS.get(method, method), variant, ctypes.byref(bm), ctypes.byref(bn),
                                 ctypes.byref(bk)))
     return bm.value, bn.value, bk.value
+
+
+PAIR_BASE = 64   # MM_PAIR_BASE: grouped variant id of size-class pair 0
+
+
+def grouped_pair_count(method) -> int:
+    return int(lib().mm_grouped_pair_count(METHODS.get(method, method)))
+
+
+def grouped_pair_info(method, pair: int):
+    """(small variant, large variant, pct) of size-class pair `pair`; its
+    grouped variant id is PAIR_BASE + pair."""
+    s, l, pct = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check(lib().mm_grouped_pair_info(METHODS.get(method, method), pair, ctypes.byref(s), ctypes.byref(l),
+                                     ctypes.byref(pct)))
+    return s.value, l.value, pct.value
 
 
 def select_variant(method, M, N, K) -> int:

@@ -267,6 +267,10 @@ mm_status mm_grouped_autotune(const mm_problem *probs, int32_t count, mm_method 
         if (count <= 0 || !probs) return fail(MM_E_INVAL, "autotune needs a non-empty batch");
         const int nv = mm_variant_count(method);
         if (nv <= 0) return fail(MM_E_INVAL, "unknown method");
+        // every tile variant, then every size-class pair
+        std::vector<int> ids;
+        for (int v = 0; v < nv; ++v) ids.push_back(v);
+        for (int p = 0; p < grouped_pair_count(method); ++p) ids.push_back(MM_PAIR_BASE + p);
         hipStream_t st = (hipStream_t)stream;
         hipEvent_t e0, e1;
         MM_HIP(hipEventCreate(&e0));
@@ -274,7 +278,8 @@ mm_status mm_grouped_autotune(const mm_problem *probs, int32_t count, mm_method 
         int best_v = -1, best_s = 0;
         double best_ms = 0;
         mm_status status = MM_OK;
-        for (int v = 0; v < nv && status == MM_OK; ++v) {
+        for (size_t vi = 0; vi < ids.size() && status == MM_OK; ++vi) {
+            const int v = ids[vi];
             for (int sch = 0; sch <= 3 && status == MM_OK; ++sch) {
                 mm_grouped_plan *plan = nullptr;
                 std::vector<float> times;
@@ -402,8 +407,11 @@ mm_status mm_autotune_load(const char *path) {
                 return fail(MM_E_INVAL, "malformed entry");
             const int k0 = (int)v[0], variant = (int)v[4], schedule = (int)v[6];
             const int method = k0 >= 100 ? k0 - 100 : k0;
-            if (method < 0 || method > 3 || variant < 0 || variant >= mm_variant_count((mm_method)method) ||
-                schedule < 0 || schedule > 3)
+            // grouped entries (key 100 + method) may name a size-class pair
+            const bool known = method >= 0 && method <= 3 &&
+                               (k0 >= 100 ? grouped_variant_valid((mm_method)method, variant)
+                                          : variant >= 0 && variant < mm_variant_count((mm_method)method));
+            if (!known || schedule < 0 || schedule > 3)
                 return fail(MM_E_INVAL, "entry names an unknown method, variant or schedule");
             fresh[Key(k0, (int)v[1], (int)v[2], (int)v[3])] = Entry{variant, v[5], schedule};
             p = close + 1;

@@ -1,6 +1,10 @@
 // Grouped products: many independent C_i = A_i.B_i of different shapes in one
 // persistent launch.
 //
+// Size-class pairs run each problem on the smaller or the larger of two tile
+// variants of one workgroup size (chosen on the host from the padded work of
+// each); the tile table carries each tile's kind.
+//
 // Tile map: problem i contributes ceil(M_i/BM) * ceil(N_i/BN) tiles; the host
 // stores the exclusive prefix sum of these counts in each descriptor.  A
 // persistent grid (the number of workgroups the chip holds at once) walks the
@@ -215,6 +219,60 @@ __global__ __launch_bounds__(ST::NT, PERSISTENT ? (ST::NWAVES >= 8 ? 2 : 1) : Sp
     }
 }
 
+// Size-class pair kernels.  Each tile's kind, read from the tile table (which
+// these launches always have), picks the small or the large variant's tile
+// body; the two share the workgroup size and one LDS array (the larger of
+// their two).  Same two forms as above.
+template <typename TS, typename TL> struct PairLds {
+    static constexpr int value = TS::LDS_ELEMS > TL::LDS_ELEMS ? TS::LDS_ELEMS : TL::LDS_ELEMS;
+};
+
+template <typename TS, typename TL, typename E, bool SPLIT>
+__device__ __forceinline__ void grouped_pair_tile(const GroupedDesc *__restrict__ descs,
+                                                  const TileRef *__restrict__ tiles, int64_t t, E *smem) {
+    const TileRef r = tiles[t];
+    const GroupedDesc &d = descs[uniform(r.own)];
+    const int64_t tm = uniform(r.tm), tn = uniform(r.tn);
+    if constexpr (SPLIT) {
+        static_assert(TS::FUSED && TL::FUSED, "split pairs read the FP32 operands (no plane pass)");
+        if (uniform(r.kind)) grouped_split_tile<TL>(d, tm, tn, smem);
+        else grouped_split_tile<TS>(d, tm, tn, smem);
+    } else {
+        if (uniform(r.kind)) grouped_dense_tile<TL, E>(d, tm, tn, smem);
+        else grouped_dense_tile<TS, E>(d, tm, tn, smem);
+    }
+}
+
+// Waves per SIMD the pair kernels are compiled for: what the dense and split
+// kernels above ask of their tile, for the pair's larger LDS array.
+template <typename TS, typename TL, typename E, bool SPLIT, bool PERSISTENT> struct PairWaves {
+    static constexpr int dense = TS::NWAVES <= 4 && PairLds<TS, TL>::value * sizeof(E) <= 76 * 1024 ? 2 : 1;
+    static constexpr int split_tile = SplitWaves<TS>::value < SplitWaves<TL>::value ? SplitWaves<TS>::value
+                                                                                    : SplitWaves<TL>::value;
+    static constexpr int value = !SPLIT ? dense : PERSISTENT ? (TS::NWAVES >= 8 ? 2 : 1) : split_tile;
+};
+
+template <typename TS, typename TL, typename E, bool SPLIT, bool PERSISTENT>
+__global__ __launch_bounds__(TS::NT, (PairWaves<TS, TL, E, SPLIT, PERSISTENT>::value)) void grouped_pair_kernel(
+    const GroupedDesc *__restrict__ descs, int count, int64_t total_tiles, int *counter,
+    const TileRef *__restrict__ tiles) {
+    static_assert(TS::NT == TL::NT, "the two variants of a pair share one workgroup size");
+    __shared__ __attribute__((aligned(16))) E smem[PairLds<TS, TL>::value];
+    (void)count;
+    if constexpr (PERSISTENT) {
+        __shared__ int64_t slot;
+        for (int64_t t = blockIdx.x; t < total_tiles;) {
+            const int ticket = draw_ticket(counter);
+            grouped_pair_tile<TS, TL, E, SPLIT>(descs, tiles, t, smem);
+            __syncthreads();
+            t = next_tile(t, counter, ticket, &slot);
+        }
+    } else {
+        const int64_t t = chunked_tile(blockIdx.x);
+        if (t < total_tiles) grouped_pair_tile<TS, TL, E, SPLIT>(descs, tiles, t, smem);
+    }
+}
+
 // Streamed persistent form of the fused ring tiles: each workgroup runs its
 // sequence of tiles as one stream of K steps, loading the next tile's first
 // steps while the current tile is multiplied (SplitTileFusedRing::run_stream).
@@ -356,6 +414,7 @@ struct KernelInfo {
     KernelPtr fn = nullptr;
     int nt = 0, bm = 0, bn = 0;
     bool stream = false;   // a streamed persistent form exists (ring-fused split tiles)
+    bool table = false;    // the kernel reads the tile table (size-class pairs)
 };
 
 // Ring-fused split tiles with one K step in flight (the only ones with a
@@ -382,7 +441,77 @@ static KernelPtr split_kernel(int form) {
 template <typename ST>
 static constexpr bool split_has_stream() { return has_ring<ST>::value; }
 
+// Tile type of each variant id, for the pair kernels.
+template <int V> struct F64Var;
+template <int V> struct F32Var;
+template <int V> struct S3Var;
+template <int V> struct S6Var;
+#define MM_TV_F64(id, bm_, bn_, bk, wm, wn, st) \
+    template <> struct F64Var<id> { typedef TileSel<double, bm_, bn_, bk, wm, wn, st>::type type; };
+#define MM_TV_F32(id, bm_, bn_, bk, wm, wn, st) \
+    template <> struct F32Var<id> { typedef TileSel<float, bm_, bn_, bk, wm, wn, st>::type type; };
+#define MM_TV_S(id, bm_, bn_, bk, wm, wn, st)                                                          \
+    template <> struct S3Var<id> { typedef SplitTileSel<3, bm_, bn_, bk, wm, wn, st>::type type; }; \
+    template <> struct S6Var<id> { typedef SplitTileSel<6, bm_, bn_, bk, wm, wn, st>::type type; };
+MM_F64_VARIANTS(MM_TV_F64)
+MM_F32_VARIANTS(MM_TV_F32)
+MM_SPLIT_VARIANTS(MM_TV_S)
+
+template <typename TS, typename TL, typename E, bool SPLIT>
+static KernelInfo pair_kernel(int form) {
+    KernelInfo k;
+    k.fn = form == kFormStream ? nullptr
+           : form == kFormTile ? (KernelPtr)&grouped_pair_kernel<TS, TL, E, SPLIT, false>
+                               : (KernelPtr)&grouped_pair_kernel<TS, TL, E, SPLIT, true>;
+    k.nt = TS::NT;
+    k.table = true;
+    return k;
+}
+
+static KernelInfo pair_kernel_for(mm_method method, int pair, int form) {
+#define MM_GP_F64(p, s_, l_, pct) case p: return pair_kernel<F64Var<s_>::type, F64Var<l_>::type, double, false>(form);
+#define MM_GP_F32(p, s_, l_, pct) case p: return pair_kernel<F32Var<s_>::type, F32Var<l_>::type, float, false>(form);
+#define MM_GP_S3(p, s_, l_, pct) case p: return pair_kernel<S3Var<s_>::type, S3Var<l_>::type, uint16_t, true>(form);
+#define MM_GP_S6(p, s_, l_, pct) case p: return pair_kernel<S6Var<s_>::type, S6Var<l_>::type, uint16_t, true>(form);
+    switch (method) {
+        case MM_F64: switch (pair) { MM_F64_PAIRS(MM_GP_F64) default: break; } break;
+        case MM_F32: switch (pair) { MM_F32_PAIRS(MM_GP_F32) default: break; } break;
+        case MM_SPLIT_BF16_3: switch (pair) { MM_SPLIT_PAIRS(MM_GP_S3) default: break; } break;
+        case MM_SPLIT_BF16_6: switch (pair) { MM_SPLIT_PAIRS(MM_GP_S6) default: break; } break;
+    }
+    return KernelInfo();
+}
+
+int grouped_pair_count(mm_method method) {
+#define MM_PAIR_ONE(p, s_, l_, pct) +1
+    switch (method) {
+        case MM_F64: return 0 MM_F64_PAIRS(MM_PAIR_ONE);
+        case MM_F32: return 0 MM_F32_PAIRS(MM_PAIR_ONE);
+        case MM_SPLIT_BF16_3:
+        case MM_SPLIT_BF16_6: return 0 MM_SPLIT_PAIRS(MM_PAIR_ONE);
+    }
+    return 0;
+}
+
+bool grouped_pair(mm_method method, int variant, PairCfg *out) {
+    const int p = variant - MM_PAIR_BASE;
+#define MM_PAIR_CFG(p_, s_, l_, pct) case p_: *out = PairCfg{s_, l_, pct}; return true;
+    switch (method) {
+        case MM_F64: switch (p) { MM_F64_PAIRS(MM_PAIR_CFG) default: return false; }
+        case MM_F32: switch (p) { MM_F32_PAIRS(MM_PAIR_CFG) default: return false; }
+        case MM_SPLIT_BF16_3:
+        case MM_SPLIT_BF16_6: switch (p) { MM_SPLIT_PAIRS(MM_PAIR_CFG) default: return false; }
+    }
+    return false;
+}
+
+bool grouped_variant_valid(mm_method method, int variant) {
+    PairCfg pc;
+    return (variant >= 0 && variant < mm_variant_count(method)) || grouped_pair(method, variant, &pc);
+}
+
 static KernelInfo kernel_for(mm_method method, int variant, int form = kFormPersistent) {
+    if (variant >= MM_PAIR_BASE) return pair_kernel_for(method, variant - MM_PAIR_BASE, form);
     KernelInfo k;
 #define MM_GK_F64(id, bm_, bn_, bk, wm, wn, st) \
     case id: { typedef TileSel<double, bm_, bn_, bk, wm, wn, st>::type TG; k.fn = form == kFormStream ? nullptr : dense_kernel<TG, double>(form); k.nt = TG::NT; k.bm = bm_; k.bn = bn_; break; }
@@ -448,16 +577,35 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+static TileCfg tile_cfg(mm_method method, int variant) {
+    return method == MM_F64 ? f64_variant(variant) : method == MM_F32 ? f32_variant(variant) : split_variant(variant);
+}
+
+// The member of a size-class pair that computes an M x N x K problem: the
+// small variant when its tiles execute at most pct % of the large one's
+// padded work (rows, columns and K rounded up to the tile), else the large.
+static int pair_kind(mm_method method, const PairCfg &pc, int64_t M, int64_t N, int64_t K) {
+    auto work = [&](int v) {
+        const TileCfg c = tile_cfg(method, v);
+        const int64_t k = K > 0 ? K : 1;
+        return (double)(cdiv(M, c.bm) * c.bm) * (double)(cdiv(N, c.bn) * c.bn) * (double)(cdiv(k, c.bk) * c.bk);
+    };
+    return work(pc.small) * 100.0 <= pc.pct * work(pc.large) ? 0 : 1;
+}
+
 // order: problem indices in launch order (schedule already applied).
 void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_method method, int variant,
                          char *ws, Layout *L) {
-    const int bm = grouped_tile_bm(method, variant), bn = grouped_tile_bn(method, variant);
+    PairCfg pc{};
+    const bool pair = grouped_pair(method, variant, &pc);
     const bool split_method = method == MM_SPLIT_BF16_3 || method == MM_SPLIT_BF16_6;
     // fused split tiles read the FP32 operands themselves: no planes, no jobs
-    const bool split = split_method && !split_variant_fused(variant);
+    // (the members of split pairs are all fused)
+    const bool split = split_method && !pair && !split_variant_fused(variant);
     const int np = method == MM_SPLIT_BF16_3 ? 2 : 3;
     L->descs.clear();
     L->jobs.clear();
+    L->kinds.clear();
     L->total_tiles = 0;
     L->split_tiles = 0;
     L->ring_ok = true;
@@ -465,6 +613,9 @@ void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_met
     for (int idx : order) {
         const mm_problem &p = probs[idx];
         if (p.M == 0 || p.N == 0) continue;
+        const int kind = pair ? pair_kind(method, pc, p.M, p.N, p.K) : 0;
+        const int v = pair ? (kind ? pc.large : pc.small) : variant;
+        const int bm = grouped_tile_bm(method, v), bn = grouped_tile_bn(method, v);
         GroupedDesc d;
         std::memset(&d, 0, sizeof d);
         d.M = p.M;
@@ -507,6 +658,7 @@ void build_layout(const mm_problem *probs, const std::vector<int> &order, mm_met
             }
         }
         L->descs.push_back(d);
+        L->kinds.push_back((int8_t)kind);
     }
     L->ws_bytes = off;
 }
@@ -527,7 +679,7 @@ void build_tile_table(const Layout &L, std::vector<TileRef> *out) {
             r.own = (int32_t)i;
             r.tm = (int32_t)(first_m + in % gsize);
             r.tn = (int32_t)(in / gsize);
-            r.pad = 0;
+            r.kind = L.kinds.empty() ? 0 : L.kinds[i];
         }
     }
 }
@@ -559,6 +711,7 @@ hipError_t grouped_enqueue(mm_method method, int variant, int form, const Groupe
     const bool persistent = form != kFormTile;
     const KernelInfo k = kernel_for(method, variant, form);
     if (!k.fn) return hipErrorInvalidValue;
+    if ((form == kFormStream || k.table) && !d_tiles) return hipErrorInvalidValue;
     if (!persistent && chunked_grid(total_tiles) > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     if (njobs > 0 && split_tiles > 0) {
         int64_t g = split_tiles < 4096 ? split_tiles : 4096;
@@ -567,7 +720,6 @@ hipError_t grouped_enqueue(mm_method method, int variant, int form, const Groupe
     if (!persistent) d_counter = nullptr;
     if (d_counter) hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, st, d_counter);
     const int64_t grid = launch_grid(form, k, total_tiles);
-    if (form == kFormStream && !d_tiles) return hipErrorInvalidValue;
     void *args[] = {(void *)&d_descs, (void *)&ndesc, (void *)&total_tiles, (void *)&d_counter, (void *)&d_tiles};
     return hipLaunchKernel(k.fn, dim3((unsigned)grid), dim3(k.nt), args, 0, st);
 }
@@ -805,7 +957,7 @@ static mm_status run_once(const mm_problem *probs, int32_t count, mm_method meth
     if (nd == 0) return MM_OK;
     const int form = grouped_form(method, variant, schedule, L);
     std::vector<TileRef> table;
-    if (form == kFormStream) build_tile_table(L, &table);
+    if (form == kFormStream || kernel_for(method, variant, form).table) build_tile_table(L, &table);
     // device buffer: descriptors | split jobs | work counters | tile table | split workspace
     const size_t desc_bytes = align256(nd * sizeof(GroupedDesc));
     const size_t job_bytes = align256(L.jobs.size() * sizeof(SplitJob) + 1);
@@ -909,7 +1061,7 @@ mm_status mm_gemm_grouped_config(const mm_problem *probs, int32_t count, mm_meth
     try {
         mm_status s = validate(probs, count, method);
         if (s != MM_OK) return s;
-        if (variant < 0 || variant >= mm_variant_count(method)) return fail(MM_E_INVAL, "no such variant");
+        if (!grouped_variant_valid(method, variant)) return fail(MM_E_INVAL, "no such variant or pair");
         if (schedule < 0 || schedule > 3) return fail(MM_E_INVAL, "schedule must be 0, 1, 2 or 3");
         hipStream_t st = (hipStream_t)stream;
         if (plan_inout && *plan_inout) {
@@ -929,6 +1081,18 @@ mm_status mm_gemm_grouped_config(const mm_problem *probs, int32_t count, mm_meth
     } catch (...) {
         return fail(MM_E_DEVICE, "internal error");
     }
+}
+
+int32_t mm_grouped_pair_count(mm_method method) { return grouped_pair_count(method); }
+
+mm_status mm_grouped_pair_info(mm_method method, int32_t pair, int32_t *small_out, int32_t *large_out,
+                               int32_t *pct_out) {
+    PairCfg pc;
+    if (pair < 0 || !grouped_pair(method, MM_PAIR_BASE + pair, &pc)) return fail(MM_E_INVAL, "no such pair");
+    if (small_out) *small_out = pc.small;
+    if (large_out) *large_out = pc.large;
+    if (pct_out) *pct_out = pc.pct;
+    return MM_OK;
 }
 
 }  // extern "C"

@@ -145,15 +145,17 @@ struct SplitJob {
 
 // Owner problem and tile coordinates of one tile of a grouped batch (the
 // kernels read these, when a launch has the table, instead of searching the
-// prefix sums).
+// prefix sums); kind: which variant of a size-class pair computes the tile
+// (0 the small one, 1 the large one; 0 in single-variant launches).
 struct TileRef {
-    int32_t own, tm, tn, pad;
+    int32_t own, tm, tn, kind;
 };
 
 // Host tile map of one grouped batch.
 struct Layout {
     std::vector<GroupedDesc> descs;
     std::vector<SplitJob> jobs;
+    std::vector<int8_t> kinds;   // per descriptor: the pair member it runs on (pair launches)
     int64_t total_tiles = 0;
     int64_t split_tiles = 0;
     size_t ws_bytes = 0;  // split planes of the whole batch
@@ -162,6 +164,12 @@ struct Layout {
 
 int grouped_tile_bm(mm_method method, int variant);
 int grouped_tile_bn(mm_method method, int variant);
+// Size-class pairs (grouped variant ids MM_PAIR_BASE + p).
+struct PairCfg { int small, large, pct; };
+int grouped_pair_count(mm_method method);
+bool grouped_pair(mm_method method, int variant, PairCfg *out);
+// A tile variant of the method or one of its pairs.
+bool grouped_variant_valid(mm_method method, int variant);
 // Launch order of the problems for a schedule (0: as given; 1, 2: heaviest first).
 std::vector<int> schedule_order(const mm_problem *probs, int count, int schedule);
 // Descriptors (and, for plane-reading split variants, split jobs with planes

@@ -76,3 +76,21 @@
     X(16, 128, 64, 32, 64, 32, 31)    \
     X(17, 64, 64, 32, 32, 32, 21)     \
     X(18, 128, 64, 32, 64, 32, 21)
+
+// Size-class pairs of grouped launches: X(pair, small, large, pct).  Grouped
+// variant id MM_PAIR_BASE + pair runs each problem of a batch on one of two
+// variants of the same workgroup size: the small one when its tiles execute
+// at most pct % of the large one's padded work (edge and K padding), else the
+// large one.  Split pairs are ring-fused variants (no plane pass).
+#define MM_F64_PAIRS(X)    \
+    X(0, 16, 7, 90)        \
+    X(1, 16, 6, 90)        \
+    X(2, 14, 7, 80)
+#define MM_F32_PAIRS(X)    \
+    X(0, 15, 8, 90)        \
+    X(1, 15, 8, 80)
+#define MM_SPLIT_PAIRS(X)  \
+    X(0, 15, 16, 90)       \
+    X(1, 15, 16, 75)       \
+    X(2, 17, 18, 90)       \
+    X(3, 17, 18, 75)

@@ -144,6 +144,35 @@ def test_variant_tables(lib):
         assert bm <= 64 and bn <= 64
 
 
+def test_grouped_pairs(lib):
+    # size-class pairs: two variants of one workgroup size per pair, ids from
+    # MM_PAIR_BASE (the value the binding mirrors), accepted by the grouped
+    # entry points' argument checks and rejected past the table
+    hdr = open(HEADER).read()
+    assert re.search(r"#define MM_PAIR_BASE (\d+)", hdr).group(1) == str(api.PAIR_BASE)
+    for m in ("f64", "f32", "split3", "split6"):
+        n = api.grouped_pair_count(m)
+        assert n >= 2
+        for p in range(n):
+            small, large, pct = api.grouped_pair_info(m, p)
+            bs, bl = api.variant_info(m, small), api.variant_info(m, large)
+            assert bs[0] * bs[1] < bl[0] * bl[1] and bs[2] == bl[2]   # smaller tile, same K step
+            assert 0 < pct <= 100
+            if m.startswith("split"):
+                assert small >= 15 and large >= 15                   # ring-fused members
+        with pytest.raises(api.MMError):
+            api.grouped_pair_info(m, n)
+        with pytest.raises(api.MMError):
+            api.grouped_pair_info(m, -1)
+    p = 1 << 20
+    probs = (api.Problem * 1)(api.Problem(4, 4, 4, p, 4, p, 4, p * 4, 4))
+    n = api.grouped_pair_count("f64")
+    assert lib.mm_gemm_grouped_config(probs, 0, api.MM_F64, api.PAIR_BASE + n - 1, 3, None, None) == api.MM_OK
+    assert lib.mm_gemm_grouped_config(probs, 0, api.MM_F64, api.PAIR_BASE + n, 3, None, None) == api.MM_E_INVAL
+    assert b"pair" in lib.mm_last_error()
+    assert lib.mm_gemm_grouped_config(probs, 0, api.MM_F64, api.variant_count("f64"), 3, None, None) == api.MM_E_INVAL
+
+
 def test_autotune_cache_roundtrip(lib, tmp_path):
     path = str(tmp_path / "cache.json")
     api.autotune_clear()
@@ -170,9 +199,25 @@ def test_autotune_cache_roundtrip(lib, tmp_path):
     json.dump(doc, open(path, "w"))
     with pytest.raises(api.MMError):
         api.autotune_load(path)
+    # a size-class pair is a grouped variant only
+    doc["entries"] = [[api.MM_F64, 10, 10, 10, api.PAIR_BASE, 1.5, 0]]
+    json.dump(doc, open(path, "w"))
+    with pytest.raises(api.MMError):
+        api.autotune_load(path)
+    doc["entries"] = [[100 + api.MM_F64, 9, 18, 9, api.PAIR_BASE, 1.5, 3],
+                      [100 + api.MM_F64, 9, 18, 10, api.PAIR_BASE + api.grouped_pair_count("f64"), 1.5, 3]]
+    json.dump(doc, open(path, "w"))
+    with pytest.raises(api.MMError):
+        api.autotune_load(path)
     assert api.select_variant("f64", 1000, 1000, 1000) == other
     api.autotune_clear()
     assert api.select_variant("f64", 1000, 1000, 1000) == default
+    doc["entries"] = [[100 + api.MM_F64, 9, 18, 9, api.PAIR_BASE + 1, 1.5, 3]]
+    json.dump(doc, open(path, "w"))
+    api.autotune_load(path)
+    api.autotune_save(path)
+    assert json.load(open(path))["entries"] == [[100 + api.MM_F64, 9, 18, 9, api.PAIR_BASE + 1, 1.5, 3]]
+    api.autotune_clear()
 
 
 def test_binding_rejects_views_that_are_not_row_major_matrices():

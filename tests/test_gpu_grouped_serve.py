@@ -171,6 +171,63 @@ def test_grouped_every_split_variant(mm, method):
     check_oracle(method, hostAB, Cs, range(len(shapes)))
 
 
+def pair_member(mm, method, pair, M, N, K):
+    """The variant size-class pair `pair` runs an M x N x K problem on: the
+    small one when its tiles execute at most pct % of the large one's padded
+    work (rows, columns and K rounded up to the tile), else the large one."""
+    small, large, pct = mm.grouped_pair_info(method, pair)
+
+    def work(v):
+        bm, bn, bk = mm.variant_info(method, v)
+        return -(-M // bm) * bm * (-(-N // bn) * bn) * (-(-max(K, 1) // bk) * bk)
+    return small if work(small) * 100 <= pct * work(large) else large
+
+
+@pytest.mark.parametrize("method", ["f64", "f32", "split3", "split6"])
+def test_grouped_size_class_pairs(mm, method):
+    """Every size-class pair under every schedule, on a ragged batch (K == 0,
+    an empty problem, 1x1x1) whose problems fall to both members: each problem
+    equals, bit for bit, the single-problem kernel of the member the pair's
+    rule picks for its shape; then a plan of the pair replayed with eager work
+    in between."""
+    shapes = ragged_shapes(40, 1, 300, seed=51)
+    As, Bs, Cs, hostAB = make_batch(method, shapes, seed=52)
+    for pair in range(mm.grouped_pair_count(method)):
+        small, large, _ = mm.grouped_pair_info(method, pair)
+        ref = {v: singles(mm, method, v, As, Bs) for v in (small, large)}
+        member = [pair_member(mm, method, pair, *sh) for sh in shapes]
+        assert small in member and large in member
+        for schedule in (0, 1, 2, 3):
+            for C in Cs:
+                C.fill_(float("nan"))
+            mm.gemm_grouped(method, As, Bs, Cs, variant=mm.PAIR_BASE + pair, schedule=schedule)
+            torch.cuda.synchronize()
+            for i, C in enumerate(Cs):
+                assert np.array_equal(C.cpu().numpy(), ref[member[i]][i]), \
+                    f"pair {pair} schedule {schedule} problem {i} shape {shapes[i]}"
+    check_oracle(method, hostAB, Cs, range(len(shapes)))
+    pair = mm.grouped_pair_count(method) - 1
+    member = [pair_member(mm, method, pair, *sh) for sh in shapes]
+    ref = {v: singles(mm, method, v, As, Bs) for v in set(member)}
+    plan = mm.GroupedPlan(method, variant=mm.PAIR_BASE + pair, schedule=3)
+    try:
+        plan.run(As, Bs, Cs)
+        assert plan.info()["graph"] and plan.info()["variant"] == mm.PAIR_BASE + pair
+        for rep in range(3):
+            for C in Cs:
+                C.fill_(float("nan"))
+            junk = torch.randn(256, 256, device="cuda").sum()
+            torch.cuda.synchronize()
+            plan.replay()
+            torch.cuda.synchronize()
+            for i, C in enumerate(Cs):
+                assert np.array_equal(C.cpu().numpy(), ref[member[i]][i]), f"replay {rep} problem {i}"
+            del junk
+    finally:
+        torch.cuda.synchronize()
+        plan.close()
+
+
 @pytest.mark.parametrize("method", ["f64", "split6"])
 def test_plan_graph_replay(mm, method):
     shapes = ragged_shapes(24, 8, 260, seed=3)
@@ -275,7 +332,8 @@ def test_autotuners(mm, tmp_path):
     shapes = ragged_shapes(16, 16, 200, seed=9)
     As, Bs, Cs, hostAB = make_batch("f32", shapes, seed=9)
     gv, gs, gms = mm.grouped_autotune("f32", As, Bs, Cs, warmup=1, reps=2)
-    assert 0 <= gv < mm.variant_count("f32") and gs in (0, 1, 2, 3) and gms > 0
+    assert (0 <= gv < mm.variant_count("f32") or 0 <= gv - mm.PAIR_BASE < mm.grouped_pair_count("f32")) \
+        and gs in (0, 1, 2, 3) and gms > 0
     plan = mm.GroupedPlan("f32")
     plan.run(As, Bs, Cs)
     torch.cuda.synchronize()
