@@ -10,10 +10,10 @@ template <typename TG, typename T>
 __global__ __launch_bounds__(TG::NT, (TG::NWAVES <= 4 ? 2 : 1)) void gemm_kernel(const T *__restrict__ A, int64_t lda, const T *__restrict__ B,
                                                       int64_t ldb, T *__restrict__ C, int64_t ldc, int64_t M,
                                                       int64_t N, int64_t K, int64_t tiles_m, int64_t tiles_n,
-                                                      int vec_ok) {
+                                                      int group_m, int vec_ok) {
     __shared__ __attribute__((aligned(16))) T smem[TG::LDS_ELEMS];
     int64_t tm, tn;
-    tile_order(blockIdx.x, tiles_m, tiles_n, 8, &tm, &tn);
+    tile_order(blockIdx.x, tiles_m, tiles_n, group_m, &tm, &tn);
     TG::run(A, lda, B, ldb, C, ldc, M, N, K, tm, tn, vec_ok != 0, smem);
 }
 
@@ -28,8 +28,9 @@ static hipError_t launch_tile(int64_t M, int64_t N, int64_t K, const T *A, int64
     const int vec = TG::VEC;
     const int vec_ok = (lda % vec == 0) && (ldb % vec == 0) && ((uintptr_t)A % 16 == 0) &&
                        ((uintptr_t)B % 16 == 0);
+    static const int group = tile_group_rows((const void *)&gemm_kernel<TG, T>, TG::NT, TG::BM, TG::BN);
     hipLaunchKernelGGL((gemm_kernel<TG, T>), dim3((unsigned)blocks), dim3(TG::NT), 0, stream, A, lda, B, ldb, C,
-                       ldc, M, N, K, tiles_m, tiles_n, vec_ok);
+                       ldc, M, N, K, tiles_m, tiles_n, group, vec_ok);
     return hipGetLastError();
 }
 

@@ -30,6 +30,20 @@ mm_status check_gemm_args(int64_t M, int64_t N, int64_t K, const void *A, int64_
         if (_e != hipSuccess) return ::mm::hip_fail(_e, #call);        \
     } while (0)
 
+// Tile rows per group of the single-product tile order (tile_order in
+// gemm_tile.h) for `kernel`, launched with nt threads per BM x BN tile.  The R
+// workgroups resident on one XCD at a time (its 32 CUs times the kernel's
+// workgroups per CU) then cover about g tile rows by R/g tile columns; each K
+// step they fetch g A slices and R/g B slices from beyond the L2, so over the
+// product A is re-fetched once per window of columns and B once per window of
+// rows.  For a square product the sum is least at g = sqrt(R * BN / BM).
+inline int tile_group_rows(const void *kernel, int nt, int bm, int bn) {
+    int per_cu = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, nt, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    const double r = __builtin_sqrt(32.0 * per_cu * bn / bm);
+    return r < 1.0 ? 1 : (int)(r + 0.5);
+}
+
 // Per-device facts, filled once.
 struct DeviceInfo {
     int device = -1;

@@ -173,20 +173,21 @@ template <typename ST>
 __global__ __launch_bounds__(ST::NT, (ST::NWAVES >= 8 ? 2 : 1)) void split_gemm_kernel(const uint16_t *__restrict__ Ap, int64_t pa_stride,
                                                             const uint16_t *__restrict__ Bt, int64_t pb_stride,
                                                             void *C, int64_t ldc, int c_is_f64, int64_t M, int64_t N,
-                                                            int64_t K, int64_t tiles_m, int64_t tiles_n, int vec_ok) {
+                                                            int64_t K, int64_t tiles_m, int64_t tiles_n, int group_m,
+                                                            int vec_ok) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
     int64_t tm, tn;
-    tile_order(blockIdx.x, tiles_m, tiles_n, 8, &tm, &tn);
+    tile_order(blockIdx.x, tiles_m, tiles_n, group_m, &tm, &tn);
     ST::run(Ap, pa_stride, Bt, pb_stride, C, ldc, c_is_f64, M, N, K, tm, tn, vec_ok != 0, smem);
 }
 
 template <typename ST>
 __global__ __launch_bounds__(ST::NT, SplitWaves<ST>::value) void split_fused_kernel(
     const float *__restrict__ A, int64_t lda, const float *__restrict__ B, int64_t ldb, void *C, int64_t ldc,
-    int c_is_f64, int64_t M, int64_t N, int64_t K, int64_t tiles_m, int64_t tiles_n) {
+    int c_is_f64, int64_t M, int64_t N, int64_t K, int64_t tiles_m, int64_t tiles_n, int group_m) {
     __shared__ __attribute__((aligned(16))) uint16_t smem[ST::LDS_ELEMS];
     int64_t tm, tn;
-    tile_order(blockIdx.x, tiles_m, tiles_n, 8, &tm, &tn);
+    tile_order(blockIdx.x, tiles_m, tiles_n, group_m, &tm, &tn);
     ST::run_fused(A, lda, B, ldb, C, ldc, c_is_f64, M, N, K, tm, tn, smem);
 }
 
@@ -201,8 +202,9 @@ static hipError_t launch_fused_tile(int64_t M, int64_t N, int64_t K, const float
         const int64_t blocks = tiles_m * tiles_n;
         if (blocks <= 0) return hipSuccess;
         if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+        static const int group = tile_group_rows((const void *)&split_fused_kernel<ST>, ST::NT, ST::BM, ST::BN);
         hipLaunchKernelGGL((split_fused_kernel<ST>), dim3((unsigned)blocks), dim3(ST::NT), 0, stream, A, lda, B, ldb,
-                           C, ldc, c_is_f64, M, N, K, tiles_m, tiles_n);
+                           C, ldc, c_is_f64, M, N, K, tiles_m, tiles_n, group);
         return hipGetLastError();
     }
 }
@@ -219,8 +221,9 @@ static hipError_t launch_split_tile(int64_t M, int64_t N, int64_t K, const uint1
         if (blocks <= 0) return hipSuccess;
         if (blocks > 0x7fffffffLL) return hipErrorInvalidConfiguration;
         const int vec_ok = (K % 8 == 0) && ((uintptr_t)Ap % 16 == 0) && ((uintptr_t)Bt % 16 == 0);
+        static const int group = tile_group_rows((const void *)&split_gemm_kernel<ST>, ST::NT, ST::BM, ST::BN);
         hipLaunchKernelGGL((split_gemm_kernel<ST>), dim3((unsigned)blocks), dim3(ST::NT), 0, stream, Ap, M * K, Bt,
-                           N * K, C, ldc, c_is_f64, M, N, K, tiles_m, tiles_n, vec_ok);
+                           N * K, C, ldc, c_is_f64, M, N, K, tiles_m, tiles_n, group, vec_ok);
         return hipGetLastError();
     }
 }
