@@ -67,6 +67,9 @@ struct Candidate {
 // FP32 adds the 16-wave 256x256 ring (64x64 wave tiles: half the fragment
 // reads and barriers per product of the 256x128 one; 146.5 against 142.6
 // TFLOP/s at 8192, +2.7% at 4096 and 16384).
+// The 16-wave 128x128 binary64 ring (32x32 wave tiles, K step 32) is the
+// large candidate: 15.32 against 15.44 ms for the 256x128 ring at 8192, 6.49
+// against 7.25-7.30 at 6144, equal at 4096, and the best at 1792-2048.
 // The binary64 64x64 candidate is the 16-wave ring (16x16 wave tiles, K step
 // 32): four waves per SIMD where one 64x64 tile per CU leaves the 4-wave ring
 // one (1024: 43-46 against 47-48 us; 6144: 6.99 against 7.27 ms; equal at
@@ -78,8 +81,8 @@ struct Candidate {
 // 64x64 one: even on a grid of equal rounds (2048: 149 against 141 us) it is
 // within 6%, and it wins where it leaves fewer rounds (1536: +14%, 1792: +5%,
 // 2560: +2%).
-const Candidate kF64Cand[] = {{15, 256, 128, 71.0, false}, {3, 128, 64, 56.5, false}, {17, 64, 64, 67.5, false},
-                              {14, 32, 32, 52.0, false}, {16, 64, 32, 60.0, false}};
+const Candidate kF64Cand[] = {{18, 128, 128, 71.6, false}, {15, 256, 128, 71.0, false}, {3, 128, 64, 56.5, false},
+                              {17, 64, 64, 67.5, false}, {14, 32, 32, 52.0, false}, {16, 64, 32, 60.0, false}};
 const Candidate kF32Cand[] = {{14, 256, 256, 146.5, false}, {13, 256, 128, 142.6, false}, {3, 128, 128, 126.5, false},
                               {8, 64, 64, 141.0, false}, {10, 32, 32, 95.0, false}, {15, 32, 64, 134.0, false}};
 const Candidate kSplit3Unfused[] = {{14, 256, 128, 438.0, true}, {6, 128, 128, 364.0, true}, {8, 64, 64, 319.0, true}};

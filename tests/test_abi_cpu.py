@@ -134,11 +134,11 @@ def test_variant_tables(lib):
         with pytest.raises(api.MMError):
             api.variant_info(m, n)
     # selection is a pure function of the shape: large products take a
-    # 256-row tile (256x256 for FP32, 256x128 otherwise), small ones a tile of
-    # at most 64x64
+    # large tile (binary64 128x128 with 16 waves, FP32 256x256, the split
+    # methods 256x128), small ones a tile of at most 64x64
     assert api.select_variant("f64", 8192, 8192, 8192) == api.select_variant("f64", 8192, 8192, 8192)
     for m in ("f64", "f32", "split3", "split6"):
-        big = (256, 256) if m == "f32" else (256, 128)
+        big = {"f64": (128, 128), "f32": (256, 256)}.get(m, (256, 128))
         assert api.variant_info(m, api.select_variant(m, 8192, 8192, 8192))[:2] == big
         bm, bn, _ = api.variant_info(m, api.select_variant(m, 256, 256, 256))
         assert bm <= 64 and bn <= 64
