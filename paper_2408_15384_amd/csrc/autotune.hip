@@ -70,6 +70,11 @@ struct Candidate {
 // The 16-wave 128x128 binary64 ring (32x32 wave tiles, K step 32) is the
 // large candidate: 15.32 against 15.44 ms for the 256x128 ring at 8192, 6.49
 // against 7.25-7.30 at 6144, equal at 4096, and the best at 1792-2048.
+// The binary64 32x32 candidate is the 2-buffer ring with a K step of 32 (half
+// the barriers of the 16-step rings): 640: 16.4 against 20.6 us for the
+// 4-buffer 16-step ring, 768: 24.6 against 31.3, 1280: 86 against 92 (64x64),
+// 1536: 126 against 129 (64x32); 2-4% behind the 64x64 and 64x32 rings at
+// 2304-2560, which its rate leaves to them from 2560.
 // The binary64 64x64 candidate is the 16-wave ring (16x16 wave tiles, K step
 // 32): four waves per SIMD where one 64x64 tile per CU leaves the 4-wave ring
 // one (1024: 43-46 against 47-48 us; 6144: 6.99 against 7.27 ms; equal at
@@ -77,12 +82,14 @@ struct Candidate {
 // The 64x32 ring runs at 0.87x the 64x64 ring's rate on a full grid (2048:
 // 293 against 255 us) but splits the work finer, so it wins where the 64x64
 // grid leaves its last round of CUs mostly empty (1536: 131 against 147 us,
-// 1792: 209 against 221).  The FP32 32x64 ring does the same for the FP32
+// 1792: 209 against 221); the 32x32 ring with a K step of 32 has since taken
+// those sizes, and the rate here (58) leaves it the near-ties only.  The FP32
+// 32x64 ring does the same for the FP32
 // 64x64 one: even on a grid of equal rounds (2048: 149 against 141 us) it is
 // within 6%, and it wins where it leaves fewer rounds (1536: +14%, 1792: +5%,
 // 2560: +2%).
 const Candidate kF64Cand[] = {{18, 128, 128, 71.6, false}, {15, 256, 128, 71.0, false}, {3, 128, 64, 56.5, false},
-                              {17, 64, 64, 67.5, false}, {14, 32, 32, 52.0, false}, {16, 64, 32, 60.0, false}};
+                              {17, 64, 64, 67.5, false}, {19, 32, 32, 59.5, false}, {16, 64, 32, 58.0, false}};
 const Candidate kF32Cand[] = {{14, 256, 256, 146.5, false}, {13, 256, 128, 142.6, false}, {3, 128, 128, 126.5, false},
                               {8, 64, 64, 141.0, false}, {10, 32, 32, 95.0, false}, {15, 32, 64, 134.0, false}};
 const Candidate kSplit3Unfused[] = {{14, 256, 128, 438.0, true}, {6, 128, 128, 364.0, true}, {8, 64, 64, 319.0, true}};

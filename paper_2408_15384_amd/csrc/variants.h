@@ -27,7 +27,8 @@
     X(15, 256, 128, 16, 64, 32, 12)   \
     X(16, 64, 32, 16, 32, 16, 12)     \
     X(17, 64, 64, 32, 16, 16, 12)     \
-    X(18, 128, 128, 32, 32, 32, 12)
+    X(18, 128, 128, 32, 32, 32, 12)   \
+    X(19, 32, 32, 32, 16, 16, 12)
 
 #define MM_F32_VARIANTS(X)            \
     X(0, 128, 128, 16, 64, 64, 0)     \
