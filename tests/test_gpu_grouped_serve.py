@@ -171,6 +171,26 @@ def test_grouped_every_split_variant(mm, method):
     check_oracle(method, hostAB, Cs, range(len(shapes)))
 
 
+@pytest.mark.parametrize("method", ["f64", "f32"])
+def test_grouped_every_dense_variant(mm, method):
+    """Every dense tile variant (4-wave and 16-wave workgroups, register-staged
+    and direct rings of 2-4 buffers, K steps of 16 and 32) in the persistent
+    form with a work counter and with one workgroup per tile, on a ragged
+    batch: grouped == single, bit for bit."""
+    shapes = ragged_shapes(24, 1, 300, seed=61)
+    As, Bs, Cs, hostAB = make_batch(method, shapes, seed=62)
+    for variant in range(mm.variant_count(method)):
+        ref = singles(mm, method, variant, As, Bs)
+        for schedule in (2, 3):
+            for C in Cs:
+                C.fill_(float("nan"))
+            mm.gemm_grouped(method, As, Bs, Cs, variant=variant, schedule=schedule)
+            torch.cuda.synchronize()
+            for i, C in enumerate(Cs):
+                assert np.array_equal(C.cpu().numpy(), ref[i]), f"variant {variant} schedule {schedule} problem {i}"
+    check_oracle(method, hostAB, Cs, range(len(shapes)))
+
+
 def pair_member(mm, method, pair, M, N, K):
     """The variant size-class pair `pair` runs an M x N x K problem on: the
     small one when its tiles execute at most pct % of the large one's padded
