@@ -168,12 +168,13 @@ int select_grouped(const mm_problem *probs, int count, mm_method method, int *sc
             return it->second.variant;
         }
     }
-    // untuned batches: 64x64 tiles (the ring-fused split for the split
-    // methods), one workgroup per tile -- among the autotuner's best on the
-    // 512-problem batch of dimensions 32..1024
+    // untuned batches: 64x64 tiles (the 2-buffer direct ring for binary64,
+    // the ring-fused split for the split methods), one workgroup per tile --
+    // among the autotuner's best on the 512-problem batch of dimensions
+    // 32..1024 (binary64: 0.584 ms against 0.607-0.653 for the 3-buffer ring)
     *schedule = 3;
     switch (method) {
-        case MM_F64: return 6;
+        case MM_F64: return 7;
         case MM_F32: return 8;
         default: return 15;
     }
