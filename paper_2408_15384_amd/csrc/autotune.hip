@@ -157,8 +157,21 @@ Key grouped_key(const mm_problem *probs, int count, mm_method method) {
 
 }  // namespace
 
-// Default for grouped batches: the smallest tile (many small problems are
-// dominated by tile quantisation and balance), heaviest problems first.
+// Tile variant of untuned grouped batches: 64x64 tiles (the 2-buffer direct
+// ring for binary64 and FP32, the ring-fused split for the split methods) --
+// among the autotuner's best on the 512-problem batch of dimensions 32..1024
+// (binary64: 0.584 ms against 0.607-0.653 for the 3-buffer ring).
+int default_grouped_variant(mm_method method) {
+    switch (method) {
+        case MM_F64: return 7;
+        case MM_F32: return 8;
+        default: return 15;
+    }
+}
+
+// Default for grouped batches: 64x64 tiles (many small problems are dominated
+// by tile quantisation and balance), heaviest problems first, one workgroup
+// per tile.
 int select_grouped(const mm_problem *probs, int count, mm_method method, int *schedule) {
     {
         std::lock_guard<std::mutex> lock(g_mu);
@@ -168,16 +181,8 @@ int select_grouped(const mm_problem *probs, int count, mm_method method, int *sc
             return it->second.variant;
         }
     }
-    // untuned batches: 64x64 tiles (the 2-buffer direct ring for binary64,
-    // the ring-fused split for the split methods), one workgroup per tile --
-    // among the autotuner's best on the 512-problem batch of dimensions
-    // 32..1024 (binary64: 0.584 ms against 0.607-0.653 for the 3-buffer ring)
     *schedule = 3;
-    switch (method) {
-        case MM_F64: return 7;
-        case MM_F32: return 8;
-        default: return 15;
-    }
+    return default_grouped_variant(method);
 }
 
 void store_grouped(const mm_problem *probs, int count, mm_method method, int variant, int schedule, double ms) {

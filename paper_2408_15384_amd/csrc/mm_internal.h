@@ -224,6 +224,8 @@ inline bool direct_operands(const void *A, int64_t lda, const void *B, int64_t l
 // Variant and schedule of a grouped launch: the cache entry of the batch's
 // bucket (method, count, mean M, mean N, mean K) if present, else a size rule.
 int select_grouped(const mm_problem *probs, int count, mm_method method, int *schedule);
+// The variant of untuned grouped batches (and of the server's small class).
+int default_grouped_variant(mm_method method);
 void store_grouped(const mm_problem *probs, int count, mm_method method, int variant, int schedule, double ms);
 
 }  // namespace mm

@@ -87,9 +87,10 @@ uint64_t request_bytes(const mm_problem &p, mm_method m, bool planes) {
 }
 
 // Default variant per method and size class: the single-product rule for a
-// 2048^3 (large) or 256^3 (small) product.
+// 2048^3 product (large), the untuned grouped batch's tile (small: a batch of
+// small requests is one grouped launch of many small problems).
 int default_serve_variant(mm_method m, bool large) {
-    return large ? select_variant(m, 2048, 2048, 2048) : select_variant(m, 256, 256, 256);
+    return large ? select_variant(m, 2048, 2048, 2048) : default_grouped_variant(m);
 }
 
 }  // namespace
