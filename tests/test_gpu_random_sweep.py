@@ -93,7 +93,22 @@ def test_random_case(mm, i):
     assert np.all(np.abs(C.astype(np.float64) - R) <= bound), case
 
 
-GROUPED_CASES = 16
+GROUPED_CASES = 32
+
+
+def pair_member(mm, method, variant, M, N, K):
+    """The tile variant a grouped variant id runs an M x N x K problem on: the
+    id itself, or for a size-class pair its small member when that member's
+    tiles execute at most pct % of the large one's padded work, else its large
+    member."""
+    if variant < mm.PAIR_BASE:
+        return variant
+    small, large, pct = mm.grouped_pair_info(method, variant - mm.PAIR_BASE)
+
+    def work(v):
+        bm, bn, bk = mm.variant_info(method, v)
+        return -(-M // bm) * bm * (-(-N // bn) * bn) * (-(-max(K, 1) // bk) * bk)
+    return small if work(small) * 100 <= pct * work(large) else large
 
 
 @pytest.mark.parametrize("i", range(GROUPED_CASES))
@@ -104,7 +119,11 @@ def test_random_grouped(mm, i):
     nothing outside the C matrices is written."""
     rng = np.random.default_rng((2026, i))
     method = METHODS[i % 4]
-    variant = int(rng.integers(0, mm.variant_count(method)))
+    # a tile variant or a size-class pair (grouped ids PAIR_BASE + p)
+    nv = mm.variant_count(method)
+    variant = int(rng.integers(0, nv + mm.grouped_pair_count(method)))
+    if variant >= nv:
+        variant = mm.PAIR_BASE + variant - nv
     schedule = int(rng.integers(0, 4))
     count = int(rng.integers(1, 41))
     f64 = method == "f64"
@@ -129,7 +148,7 @@ def test_random_grouped(mm, i):
         pads, offs = lay[j]
         case = f"case {i}: {method} v{variant} s{schedule} problem {j}/{count} M={M} N={N} K={K} pads={pads} offs={offs}"
         ref = torch.full((M, N), float("nan"), dtype=dt, device="cuda")
-        mm.gemm_variant(method, variant, As[j], Bs[j], ref)
+        mm.gemm_variant(method, pair_member(mm, method, variant, M, N, K), As[j], Bs[j], ref)
         torch.cuda.synchronize()
         C = Cs[j].cpu().numpy()
         assert np.array_equal(C, ref.cpu().numpy()), case + ": differs from the single-problem kernel"
